@@ -1,0 +1,173 @@
+"""Benchmark: DG-BGK DOF-updates/s on one MI355X.
+
+Workload: lid-driven cavity on [0,1]^2, 64 x 64 quadrilaterals, p = 3 (16 GLL
+nodes per element), Newton-Cotes 16 x 16 velocities on [-4,4]^2, Kn = 1,
+lid speed 0.1, diffuse walls, FP64, explicit RK4 at CFL 0.2 -- 16.8 M
+degrees of freedom (nodes x velocities).  One step = one RK4 step (four
+fused stage kernels); the steady-state residual is evaluated on the device
+every 50 steps inside the timed region.
+
+Prints one JSON line with the metric, a roofline object for the stage kernel
+(its average duration measured with HIP events on the stream it runs on) and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+ALG_BYTES_PER_DOF_STAGE = 32.0  # FP64 RK4, 3 registers: 24/40/40/24 B per stage -> 32 mean
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_cavity64x64_p3_nc16_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2012_13487_amd", "csrc", "kernels.hip")
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per stage launch from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken from a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha256") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(spec, budget_s):
+    """The FP64 oracle on the host's cores, on a bounded number of RK4 steps."""
+    import oracle
+    import workloads
+
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    oracle.set_threads(threads)
+    o = oracle.Oracle.from_spec(spec)
+    o.init_equilibrium()
+    dt = o.stable_dt(spec.cfl)
+    t0 = time.perf_counter()
+    o.rk4(1, dt)
+    one = time.perf_counter() - t0
+    n = max(1, min(50, int(budget_s / max(one, 1e-9)) - 1))
+    t0 = time.perf_counter()
+    o.rk4(n, dt)
+    el = time.perf_counter() - t0
+    dof = o.Q * o.K * o.Np
+    del workloads
+    return {"value": dof * 4 * n / el, "unit": "DOF-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} RK4 steps ({4 * n} stages) of the same {dof}-DOF cavity workload, "
+                      f"FP64 C oracle, OpenMP over elements"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--resid-every", type=int, default=50)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(the workload runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads
+    from paper_2012_13487_amd import Solver
+
+    torch.cuda.set_device(0)
+    spec = workloads.CAVITY_64x64_P3_NC16
+    g = Solver.from_spec(spec, stream="torch", torch_memory=True)
+    dt = g.stable_dt(spec.cfl)
+    dof = g.ndof
+    g.init_equilibrium()
+    resid = torch.zeros(max(1, args.steps // max(1, args.resid_every)) + 1,
+                        dtype=torch.float64, device="cuda")
+    if args.warmup:
+        g.step(args.warmup, dt)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    chunk = max(1, args.resid_every)
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    pairs = []
+    t_start.record(stream)
+    done, nres = 0, 0
+    while done < args.steps:
+        n = min(chunk, args.steps - done)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        g.step(n, dt)
+        b.record(stream)
+        pairs.append((a, b, n))
+        done += n
+        if done % chunk == 0:
+            g.residual_async(resid[nres].data_ptr())
+            nres += 1
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    step_ms = sum(a.elapsed_time(b) for a, b, _ in pairs)
+    stage_launches = 4 * sum(n for _, _, n in pairs)
+    stage_us = 1000.0 * step_ms / stage_launches
+    value = dof * 4 * args.steps / (total_ms / 1000.0)
+    achieved = ALG_BYTES_PER_DOF_STAGE * dof / (stage_us * 1e-6) / 1e9
+    traffic = measured_traffic()
+    res = resid[:nres].cpu().tolist()
+
+    out = {
+        "metric": "DG-BGK DOF-updates/s (nodes x velocities x RK stages)",
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "lid-driven cavity 64x64 quads p=3, NC 16x16 velocities on [-4,4]^2, "
+                        "Kn=1, lid 0.1, diffuse walls, FP64 RK4 CFL 0.2",
+            "dof": dof, "elements": g.K, "nodes_per_element": g.Np, "velocities": g.Q,
+            "dt": dt, "residual_every": args.resid_every,
+            "residual_last": res[-1] if res else None,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "stage_kernel<3>",
+            "avg_launch_us": stage_us,
+            "alg_bytes_per_launch": ALG_BYTES_PER_DOF_STAGE * dof,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * dgbgk.h -- C ABI of the MI355X (gfx950) nodal discontinuous-Galerkin
+ * discrete-Boltzmann BGK solver.
+ *
+ * Method: Ganeshan & Williams, "A finite element discrete Boltzmann method for
+ * high Knudsen number flows" (arXiv:2012.13487).  The library advances the
+ * semi-discrete system obtained from the discrete Boltzmann equation with BGK
+ * collision (Sec. II.A, eq. (6)) discretised by nodal DG (Sec. II.B, eq. (10))
+ * with an upwind numerical flux, Maxwell diffuse-reflection walls (eq. (8),
+ * imposed through the exterior state as in Sec. II.B "Implementation of
+ * boundary conditions"), and explicit classical RK4 in time (the conclusion,
+ * Sec. IV, allows explicit RK of any order).
+ *
+ * Conventions (all calls):
+ *   - uniform Cartesian quadrilaterals, element k = ex + nx*ey, ex in [0,nx),
+ *     ey in [0,ny); (p+1)^2 Gauss-Lobatto-Legendre nodes per element, node
+ *     n = i + (p+1)*j, i along x, j along y;
+ *   - distribution function stored as f[q][k][n] (velocity-major SoA), FP64 on
+ *     the host side of every call;
+ *   - sides / faces: 0 bottom (y = y0), 1 right (x = x0+lx), 2 top
+ *     (y = y0+ly), 3 left (x = x0); face nodes ordered by increasing i or j;
+ *   - 2-D tensor velocity sets: q = a + m*b with e_q = (x_a, x_b).
+ *
+ * Errors: every call returns a dgbgk_status (0 = success).  Calls that take a
+ * solver record a message readable with dgbgk_last_error(); a NULL solver
+ * returns DGBGK_EINVAL.  No exceptions cross the ABI.
+ *
+ * Ownership: the library copies every input array at the call; output arrays
+ * are owned by the caller and must hold the stated number of elements.
+ * Device memory is owned by the library unless the caller hands it a region
+ * with dgbgk_bind_buffers(), which the caller then keeps alive until
+ * dgbgk_destroy().
+ *
+ * Streams: device work is enqueued on the HIP stream given at create (NULL =
+ * the null stream).  dgbgk_step() and dgbgk_residual_async() only enqueue;
+ * calls that return host data synchronise the stream.
+ *
+ * Threads: a solver handle must be used by one host thread at a time.
+ */
+#ifndef DGBGK_H
+#define DGBGK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dgbgk_solver dgbgk_solver;
+
+typedef enum {
+  DGBGK_OK = 0,
+  DGBGK_EINVAL = -1,     /* invalid argument (message in dgbgk_last_error)   */
+  DGBGK_ENOMEM = -2,     /* host or device allocation failed                 */
+  DGBGK_EDEVICE = -3,    /* HIP runtime error or no usable gfx950 device     */
+  DGBGK_ENONFINITE = -4, /* the state or its right-hand side is not finite   */
+  DGBGK_ESTATE = -5,     /* call out of order (e.g. stepping before init)    */
+  DGBGK_ENOTSUP = -6     /* valid request this build does not implement      */
+} dgbgk_status;
+
+typedef enum { DGBGK_BC_PERIODIC = 0, DGBGK_BC_DIFFUSE_WALL = 1 } dgbgk_bc;
+
+typedef enum { DGBGK_FP64 = 0 } dgbgk_precision;
+
+/* Problem statement (Sec. II: mesh and polynomial order, velocity set and
+ * weights, relaxation time, wall and lid conditions). */
+typedef struct {
+  int32_t nx, ny;           /* elements in x and y, >= 1                      */
+  double x0, y0, lx, ly;    /* domain [x0, x0+lx] x [y0, y0+ly], lx, ly > 0    */
+  int32_t p;                /* polynomial order per direction, 1..8            */
+  int32_t q;                /* number of discrete velocities, 1..4096          */
+  const double *ex, *ey, *w;/* velocities e_q and weights w_q (length q)      */
+  double theta;             /* RT of the second-order equilibrium eq. (5), >0 */
+  double tau;               /* BGK relaxation time, > 0; +INF: collisionless  */
+  int32_t bc[4];            /* dgbgk_bc per side; periodic sides come in pairs */
+  double wall_u[4][2];      /* wall velocity per side; must be tangential     */
+} dgbgk_problem;
+
+/* ---- pure host helpers (no device use) -------------------------------- */
+
+/* 2-D tensor Gauss-Hermite set (Sec. II.A, Table I; D2Q16 = n1d 4): nodes of
+ * the n1d-point rule for the standard normal weight (RT = 1) and weights
+ * summing to one.  Writes n1d*n1d entries to ex, ey, w and theta = 1.
+ * n1d in 1..40. */
+int dgbgk_velset_gh(int32_t n1d, double *ex, double *ey, double *w, double *theta);
+
+/* 2-D tensor Newton-Cotes set (Sec. III.B): m1d equally spaced nodes on
+ * [-vmax, vmax] (units of sqrt(RT)), composite trapezoid coefficients times
+ * the Maxwellian at the node, normalised to sum one.  Writes m1d*m1d entries
+ * and theta = sum_q w_q e_qx^2 (the discrete RT that keeps eq. (5)
+ * conservative).  m1d in 2..64, vmax > 0. */
+int dgbgk_velset_nc(int32_t m1d, double vmax, double *ex, double *ey, double *w,
+                    double *theta);
+
+/* Relaxation time from the Knudsen number, eq. (7) with c_s = 1:
+ * convention 0: tau = Kn L / sqrt(3); convention 1: with Kn scaled by
+ * sqrt(pi/6) (the variant named after eq. (7)), tau = Kn L / sqrt(pi/2). */
+int dgbgk_tau_from_kn(double kn, double L, int32_t convention, double *tau);
+
+/* Bytes of device memory a solver for this problem needs (state registers,
+ * tables and scratch); the size a caller passes to dgbgk_bind_buffers(). */
+int dgbgk_required_bytes(const dgbgk_problem *pb, int32_t precision, size_t *bytes);
+
+/* ---- solver lifetime --------------------------------------------------- */
+
+/* Validates and copies the problem, builds the reference element and mesh on
+ * the host.  Touches no device: device memory is allocated (or taken from
+ * dgbgk_bind_buffers) at the first call that needs it.  hip_stream is a
+ * hipStream_t (NULL = null stream).  *out is set to NULL on failure. */
+int dgbgk_create(const dgbgk_problem *pb, int32_t precision, void *hip_stream,
+                 dgbgk_solver **out);
+
+/* Hand the solver a device region of at least dgbgk_required_bytes() bytes,
+ * 256-byte aligned, on the current device (e.g. a torch tensor's storage).
+ * Must precede the first device call. */
+int dgbgk_bind_buffers(dgbgk_solver *s, void *device_ptr, size_t bytes);
+
+/* Replace the stream used by later calls. */
+int dgbgk_set_stream(dgbgk_solver *s, void *hip_stream);
+
+void dgbgk_destroy(dgbgk_solver *s);
+
+/* Message of the last failed call on s (never NULL; "" if none). */
+const char *dgbgk_last_error(const dgbgk_solver *s);
+
+/* Version string of the library. */
+const char *dgbgk_version(void);
+
+/* ---- queries (host only) ----------------------------------------------- */
+
+/* K = nx*ny elements, Np = (p+1)^2, Nfp = p+1, Q velocities. */
+int dgbgk_sizes(const dgbgk_solver *s, int64_t *K, int32_t *Np, int32_t *Nfp, int32_t *Q);
+
+/* Explicit step for a CFL number:
+ * dt = cfl * (min(hx,hy)/2) * (smallest GLL spacing on [-1,1]) / max_q(|e_qx|+|e_qy|). */
+int dgbgk_stable_dt(const dgbgk_solver *s, double cfl, double *dt);
+
+/* Physical node coordinates, x and y of length K*Np (index k*Np + n). */
+int dgbgk_node_coords(const dgbgk_solver *s, double *x, double *y);
+
+/* Host copies of the reference-element tables (debug / tests):
+ *  0: Dr (Np x Np, row-major)   1: Ds (Np x Np)   2: M (Np x Np)
+ *  3: LIFT (Np x 4Nfp)          4: GLL nodes r (Nfp)   5: M1 (Nfp x Nfp)
+ *  6: Fscale per face (4)       7: D1 (Nfp x Nfp). */
+int dgbgk_get_operator(const dgbgk_solver *s, int32_t which, double *out);
+
+/* ---- state and marching (device) --------------------------------------- */
+
+/* f_q = f_q^eq(rho0, (ux0, uy0)) at every node (eq. (5)). */
+int dgbgk_init_equilibrium(dgbgk_solver *s, double rho0, double ux0, double uy0);
+
+/* Copy a full FP64 state f[q][k][n] (count = Q*K*Np doubles) in / out. */
+int dgbgk_set_state(dgbgk_solver *s, const double *f, size_t count);
+int dgbgk_get_state(dgbgk_solver *s, double *f, size_t count);
+
+/* Device address of the current state f[q][k][n] (FP64, Q*K*Np doubles),
+ * valid until the next dgbgk_step(); for zero-copy views. */
+int dgbgk_state_device_ptr(dgbgk_solver *s, void **ptr);
+
+/* Advance nsteps classical RK4 steps of size dt (enqueued; returns at once).
+ * Each step runs the four stages of the right-hand side
+ *   L(f)_q = -e_q . grad f_q  (volume)  + lifted upwind face flux  (surface)
+ *            - (f_q - f_q^eq(rho, u)) / tau  (collision)
+ * with rho, u and the diffuse-wall densities taken from the stage state. */
+int dgbgk_step(dgbgk_solver *s, int64_t nsteps, double dt);
+
+/* Evaluate the right-hand side L(f) for a host state f (count = Q*K*Np) into
+ * a host array k; the solver's own state is left unchanged.  Synchronises. */
+int dgbgk_rhs(dgbgk_solver *s, const double *f, double *k, size_t count);
+
+/* Diffuse-wall densities (eq. (8)) of a host state f at every face node,
+ * out[K][4][Nfp]; entries of non-wall faces are 0.  Synchronises. */
+int dgbgk_wall_density(dgbgk_solver *s, const double *f, double *out, size_t count);
+
+/* Steady-state residual of the current state:
+ *   R = max over nodes of max(|sum_q L_q|, |sum_q e_qx L_q|, |sum_q e_qy L_q|)
+ *       * L_ref / (rho_ref U_ref),
+ * rho_ref = 1, L_ref = min(lx, ly), U_ref = largest wall speed (1 if none).
+ * Synchronises; returns DGBGK_ENONFINITE (and R = NaN) for a non-finite state. */
+int dgbgk_residual(dgbgk_solver *s, double *r);
+
+/* Same as dgbgk_residual but enqueued: writes R (one double) to device memory
+ * at device_out and returns at once. */
+int dgbgk_residual_async(dgbgk_solver *s, double *device_out);
+
+/* Node moments of the current state (Sec. II.A): rho = sum_q f_q,
+ * u = sum_q e_q f_q / rho; host arrays of K*Np.  Synchronises; returns
+ * DGBGK_ENONFINITE if any value is not finite. */
+int dgbgk_moments(dgbgk_solver *s, double *rho, double *ux, double *uy);
+
+/* Wait for all work enqueued by s. */
+int dgbgk_synchronize(dgbgk_solver *s);
+
+/* Work decomposition of the stage kernel.  mode 0: automatic (all
+ * velocities of a block of elements per work-group when the tile fits in LDS,
+ * else velocity tiles); 1: force the all-velocity (fused) form; 2: force
+ * velocity tiles of velocities_per_tile (0 = largest that fits).  The tiled
+ * form reduces the node moments in a separate pass.  Results agree to
+ * rounding; this exists for testing and tuning. */
+int dgbgk_set_tiling(dgbgk_solver *s, int32_t mode, int32_t velocities_per_tile);
+int dgbgk_get_tiling(const dgbgk_solver *s, int32_t *fused, int32_t *elems_per_group,
+                     int32_t *velocities_per_tile, size_t *lds_bytes);
+
+/* Number of RK4 steps taken since the last init / set_state. */
+int dgbgk_steps_taken(const dgbgk_solver *s, int64_t *steps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGBGK_H */

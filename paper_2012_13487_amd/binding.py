@@ -1,0 +1,304 @@
+"""ctypes binding of ``libdgbgk.so`` (C ABI: include/dgbgk.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  PyTorch is used, when asked, only to provide device memory
+(``dgbgk_bind_buffers``) and the HIP stream the library enqueues on.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgbgk.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+BC_PERIODIC, BC_DIFFUSE_WALL = 0, 1
+FP64 = 0
+
+_dp = C.POINTER(C.c_double)
+
+
+class DgbgkError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"dgbgk error {code}: {message}")
+        self.code = code
+
+
+class Problem(C.Structure):
+    """Mirror of dgbgk_problem."""
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("x0", C.c_double), ("y0", C.c_double), ("lx", C.c_double), ("ly", C.c_double),
+        ("p", C.c_int32), ("q", C.c_int32),
+        ("ex", _dp), ("ey", _dp), ("w", _dp),
+        ("theta", C.c_double), ("tau", C.c_double),
+        ("bc", C.c_int32 * 4), ("wall_u", (C.c_double * 2) * 4),
+    ]
+
+
+# name -> (restype, argtypes) for every function declared in include/dgbgk.h
+SIGNATURES = {
+    "dgbgk_velset_gh": (C.c_int, [C.c_int32, _dp, _dp, _dp, _dp]),
+    "dgbgk_velset_nc": (C.c_int, [C.c_int32, C.c_double, _dp, _dp, _dp, _dp]),
+    "dgbgk_tau_from_kn": (C.c_int, [C.c_double, C.c_double, C.c_int32, _dp]),
+    "dgbgk_required_bytes": (C.c_int, [C.POINTER(Problem), C.c_int32, C.POINTER(C.c_size_t)]),
+    "dgbgk_create": (C.c_int, [C.POINTER(Problem), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "dgbgk_bind_buffers": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "dgbgk_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "dgbgk_destroy": (None, [C.c_void_p]),
+    "dgbgk_last_error": (C.c_char_p, [C.c_void_p]),
+    "dgbgk_version": (C.c_char_p, []),
+    "dgbgk_sizes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                              C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "dgbgk_stable_dt": (C.c_int, [C.c_void_p, C.c_double, _dp]),
+    "dgbgk_node_coords": (C.c_int, [C.c_void_p, _dp, _dp]),
+    "dgbgk_get_operator": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
+    "dgbgk_init_equilibrium": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double]),
+    "dgbgk_set_state": (C.c_int, [C.c_void_p, _dp, C.c_size_t]),
+    "dgbgk_get_state": (C.c_int, [C.c_void_p, _dp, C.c_size_t]),
+    "dgbgk_state_device_ptr": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "dgbgk_step": (C.c_int, [C.c_void_p, C.c_int64, C.c_double]),
+    "dgbgk_rhs": (C.c_int, [C.c_void_p, _dp, _dp, C.c_size_t]),
+    "dgbgk_wall_density": (C.c_int, [C.c_void_p, _dp, _dp, C.c_size_t]),
+    "dgbgk_residual": (C.c_int, [C.c_void_p, _dp]),
+    "dgbgk_residual_async": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "dgbgk_moments": (C.c_int, [C.c_void_p, _dp, _dp, _dp]),
+    "dgbgk_synchronize": (C.c_int, [C.c_void_p]),
+    "dgbgk_set_tiling": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "dgbgk_get_tiling": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]),
+    "dgbgk_steps_taken": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library.  Raises if it has not been built: there is no
+    fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _check(rc, handle=None):
+    if rc != OK:
+        msg = lib().dgbgk_last_error(handle).decode(errors="replace")
+        raise DgbgkError(rc, msg)
+
+
+def version():
+    return lib().dgbgk_version().decode()
+
+
+def velset_gh(n1d):
+    q = n1d * n1d
+    ex, ey, w, th = np.zeros(q), np.zeros(q), np.zeros(q), C.c_double()
+    _check(lib().dgbgk_velset_gh(n1d, _p(ex), _p(ey), _p(w), C.byref(th)))
+    return ex, ey, w, th.value
+
+
+def velset_nc(m1d, vmax):
+    q = m1d * m1d
+    ex, ey, w, th = np.zeros(q), np.zeros(q), np.zeros(q), C.c_double()
+    _check(lib().dgbgk_velset_nc(m1d, vmax, _p(ex), _p(ey), _p(w), C.byref(th)))
+    return ex, ey, w, th.value
+
+
+def velocity_set(spec):
+    """(ex, ey, w, theta) for ("gh", n) | ("nc", m, vmax) | ("custom", ex, ey, w, theta)."""
+    if spec[0] == "gh":
+        return velset_gh(spec[1])
+    if spec[0] == "nc":
+        return velset_nc(spec[1], spec[2])
+    if spec[0] == "custom":
+        return (np.ascontiguousarray(spec[1], float), np.ascontiguousarray(spec[2], float),
+                np.ascontiguousarray(spec[3], float), float(spec[4]))
+    raise ValueError(spec)
+
+
+def tau_from_kn(kn, L=1.0, convention=1):
+    t = C.c_double()
+    _check(lib().dgbgk_tau_from_kn(kn, L, convention, C.byref(t)))
+    return t.value
+
+
+def _problem(nx, ny, p, vel, tau, bc, wall_u, x0, y0, lx, ly):
+    ex, ey, w, theta = vel
+    pb = Problem()
+    pb.nx, pb.ny, pb.p, pb.q = int(nx), int(ny), int(p), len(ex)
+    pb.x0, pb.y0, pb.lx, pb.ly = x0, y0, lx, ly
+    pb.ex, pb.ey, pb.w = _p(ex), _p(ey), _p(w)
+    pb.theta, pb.tau = float(theta), float(tau)
+    for s in range(4):
+        pb.bc[s] = int(bc[s])
+        pb.wall_u[s][0], pb.wall_u[s][1] = float(wall_u[s][0]), float(wall_u[s][1])
+    return pb
+
+
+def required_bytes(nx, ny, p, vel, tau, bc, wall_u, x0=0.0, y0=0.0, lx=1.0, ly=1.0):
+    pb = _problem(nx, ny, p, vel, tau, bc, wall_u, x0, y0, lx, ly)
+    n = C.c_size_t()
+    _check(lib().dgbgk_required_bytes(C.byref(pb), FP64, C.byref(n)))
+    return n.value
+
+
+class Solver:
+    """One DG-BGK problem on the GPU.  State layout f[q][k][n], FP64.
+
+    ``stream``: a HIP stream handle (int) or "torch" for torch's current
+    stream; ``torch_memory``: take device memory from a torch tensor."""
+
+    def __init__(self, nx, ny, p, velset, tau, bc, wall_u, x0=0.0, y0=0.0, lx=1.0, ly=1.0,
+                 stream=None, torch_memory=False):
+        self._h = None
+        self.vel = velocity_set(velset)
+        self.ex, self.ey, self.w, self.theta = self.vel
+        self.tau = float(tau)
+        pb = _problem(nx, ny, p, self.vel, tau, bc, wall_u, x0, y0, lx, ly)
+        self._buf = None
+        if stream == "torch" or torch_memory:
+            import torch  # plumbing only: device memory and streams
+            if stream == "torch":
+                stream = torch.cuda.current_stream().cuda_stream
+        h = C.c_void_p()
+        _check(lib().dgbgk_create(C.byref(pb), FP64, C.c_void_p(stream or 0), C.byref(h)))
+        self._h = h.value
+        K, Np, Nfp, Q = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
+        self._call("dgbgk_sizes", C.byref(K), C.byref(Np), C.byref(Nfp), C.byref(Q))
+        self.K, self.Np, self.Nfp, self.Q = K.value, Np.value, Nfp.value, Q.value
+        self.nx, self.ny, self.p = nx, ny, p
+        self.lx, self.ly = lx, ly
+        if torch_memory:
+            import torch
+            nbytes = C.c_size_t()
+            _check(lib().dgbgk_required_bytes(C.byref(pb), FP64, C.byref(nbytes)))
+            self._buf = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+            self._call("dgbgk_bind_buffers", C.c_void_p(self._buf.data_ptr()), nbytes.value)
+
+    @classmethod
+    def from_spec(cls, spec, **kw):
+        tau = spec.tau if spec.tau is not None else tau_from_kn(spec.kn, spec.kn_length,
+                                                                spec.kn_convention)
+        return cls(spec.nx, spec.ny, spec.p, spec.velset, tau, spec.bc, spec.wall_u,
+                   spec.x0, spec.y0, spec.lx, spec.ly, **kw)
+
+    def _call(self, name, *args):
+        _check(getattr(lib(), name)(self._h, *args), self._h)
+
+    def close(self):
+        if self._h:
+            lib().dgbgk_destroy(self._h)
+            self._h = None
+        self._buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.Q, self.K, self.Np)
+
+    @property
+    def ndof(self):
+        return self.Q * self.K * self.Np
+
+    # -- host-only queries
+    def stable_dt(self, cfl):
+        dt = C.c_double()
+        self._call("dgbgk_stable_dt", cfl, C.byref(dt))
+        return dt.value
+
+    def node_coords(self):
+        x, y = np.zeros(self.K * self.Np), np.zeros(self.K * self.Np)
+        self._call("dgbgk_node_coords", _p(x), _p(y))
+        return x.reshape(self.K, self.Np), y.reshape(self.K, self.Np)
+
+    def operator(self, which):
+        n1 = self.p + 1
+        shapes = {0: (self.Np, self.Np), 1: (self.Np, self.Np), 2: (self.Np, self.Np),
+                  3: (self.Np, 4 * self.Nfp), 4: (n1,), 5: (n1, n1), 6: (4,), 7: (n1, n1)}
+        out = np.zeros(int(np.prod(shapes[which])))
+        self._call("dgbgk_get_operator", which, _p(out))
+        return out.reshape(shapes[which])
+
+    def set_tiling(self, mode, velocities_per_tile=0):
+        self._call("dgbgk_set_tiling", mode, velocities_per_tile)
+
+    def tiling(self):
+        fused, e, qt, lds = C.c_int32(), C.c_int32(), C.c_int32(), C.c_size_t()
+        self._call("dgbgk_get_tiling", C.byref(fused), C.byref(e), C.byref(qt), C.byref(lds))
+        return {"fused": bool(fused.value), "elems_per_group": e.value,
+                "velocities_per_tile": qt.value, "lds_bytes": lds.value}
+
+    # -- device work
+    def init_equilibrium(self, rho0=1.0, ux0=0.0, uy0=0.0):
+        self._call("dgbgk_init_equilibrium", rho0, ux0, uy0)
+
+    def set_state(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        self._call("dgbgk_set_state", _p(f), f.size)
+
+    def get_state(self):
+        f = np.zeros(self.ndof)
+        self._call("dgbgk_get_state", _p(f), f.size)
+        return f.reshape(self.shape)
+
+    def state_device_ptr(self):
+        ptr = C.c_void_p()
+        self._call("dgbgk_state_device_ptr", C.byref(ptr))
+        return ptr.value
+
+    def step(self, nsteps, dt):
+        self._call("dgbgk_step", int(nsteps), float(dt))
+
+    def rhs(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        k = np.zeros(self.ndof)
+        self._call("dgbgk_rhs", _p(f), _p(k), f.size)
+        return k.reshape(self.shape)
+
+    def wall_density(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        out = np.zeros(self.K * 4 * self.Nfp)
+        self._call("dgbgk_wall_density", _p(f), _p(out), f.size)
+        return out.reshape(self.K, 4, self.Nfp)
+
+    def residual(self):
+        r = C.c_double()
+        self._call("dgbgk_residual", C.byref(r))
+        return r.value
+
+    def residual_async(self, device_ptr):
+        self._call("dgbgk_residual_async", C.c_void_p(device_ptr))
+
+    def moments(self):
+        n = self.K * self.Np
+        rho, ux, uy = np.zeros(n), np.zeros(n), np.zeros(n)
+        self._call("dgbgk_moments", _p(rho), _p(ux), _p(uy))
+        return (rho.reshape(self.K, self.Np), ux.reshape(self.K, self.Np),
+                uy.reshape(self.K, self.Np))
+
+    def synchronize(self):
+        self._call("dgbgk_synchronize")
+
+    def steps_taken(self):
+        s = C.c_int64()
+        self._call("dgbgk_steps_taken", C.byref(s))
+        return s.value

@@ -1,0 +1,726 @@
+// C ABI of the DG-BGK library (declared in include/dgbgk.h).
+//
+// Host side: validation, reference-element and wall tables, device memory,
+// and the order of kernel launches for one RK4 step.  All arithmetic of the
+// time step runs in the kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dgbgk.h"
+#include "host_math.hpp"
+#include "kernels.hpp"
+
+using namespace dgbgk;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kFusedLdsLimit = 64 * 1024;  // keeps >= 2 work-groups per CU
+constexpr int kMaxQ = 4096;
+
+size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t fn, acc, a, b, vel, feqb, mom, rhow, u64, total;
+};
+
+Layout make_layout(int64_t K, int Np, int Nfp, int Q) {
+  Layout L{};
+  const size_t dof = (size_t)K * Np * Q * sizeof(double);
+  size_t off = 0;
+  L.fn = off;   off += round_up(dof);
+  L.acc = off;  off += round_up(dof);
+  L.a = off;    off += round_up(dof);
+  L.b = off;    off += round_up(dof);
+  L.vel = off;  off += round_up((size_t)3 * Q * sizeof(double));
+  L.feqb = off; off += round_up((size_t)4 * Q * sizeof(double));
+  L.mom = off;  off += round_up((size_t)3 * K * Np * sizeof(double));
+  L.rhow = off; off += round_up((size_t)K * 4 * Nfp * sizeof(double));
+  L.u64 = off;  off += round_up(8 * sizeof(unsigned long long));
+  L.total = off;
+  return L;
+}
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct dgbgk_solver {
+  dgbgk_problem pb{};
+  std::vector<double> ex, ey, w;
+  int64_t K = 0;
+  int Np = 0, Nfp = 0, Q = 0, p = 0;
+  double hx = 0, hy = 0;
+  std::vector<double> r, D1, M1, lift_lo, lift_hi;
+  std::vector<double> feqb;  // [4][Q]
+  double wall_den[4] = {0, 0, 0, 0};
+  double wall_den_inv[4] = {0, 0, 0, 0};
+  int wall_mask = 0;
+  double resid_scale = 1.0;
+  hipStream_t stream = nullptr;
+  // device
+  bool dev_ready = false;
+  void *base = nullptr;
+  bool owns = false;
+  Layout lay{};
+  double *d_fn = nullptr, *d_acc = nullptr, *d_a = nullptr, *d_b = nullptr;
+  double *d_vel = nullptr, *d_feqb = nullptr, *d_mom = nullptr, *d_rhow = nullptr;
+  unsigned long long *d_u64 = nullptr;
+  // launch configuration
+  int fused = 1, E = 1, log2E = 0, Qt = 0, ntiles = 1, nblk = 1;
+  size_t lds = 0;
+  int tiling_mode = 0, tiling_qt = 0;
+  // state
+  bool have_state = false;
+  int64_t steps = 0;
+  std::string err;
+};
+
+namespace {
+
+int fail(dgbgk_solver *s, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (s) s->err = buf;
+  else g_create_error = buf;
+  return code;
+}
+
+int hip_fail(dgbgk_solver *s, hipError_t e, const char *what) {
+  return fail(s, DGBGK_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_finite_d(double v) { return std::isfinite(v); }
+
+int validate(const dgbgk_problem *pb, dgbgk_solver *s) {
+  if (!pb) return fail(s, DGBGK_EINVAL, "problem is NULL");
+  if (pb->nx < 1 || pb->ny < 1) return fail(s, DGBGK_EINVAL, "nx, ny must be >= 1");
+  if ((int64_t)pb->nx * pb->ny > (int64_t)1 << 30)
+    return fail(s, DGBGK_EINVAL, "too many elements");
+  if (pb->p < 1 || pb->p > kMaxP) return fail(s, DGBGK_EINVAL, "p must be in 1..%d", kMaxP);
+  if (pb->q < 1 || pb->q > kMaxQ) return fail(s, DGBGK_EINVAL, "q must be in 1..%d", kMaxQ);
+  if (!pb->ex || !pb->ey || !pb->w) return fail(s, DGBGK_EINVAL, "velocity arrays are NULL");
+  if (!(pb->lx > 0) || !(pb->ly > 0) || !is_finite_d(pb->lx) || !is_finite_d(pb->ly) || !is_finite_d(pb->x0) ||
+      !is_finite_d(pb->y0))
+    return fail(s, DGBGK_EINVAL, "domain must be finite with lx, ly > 0");
+  if (!(pb->theta > 0) || !is_finite_d(pb->theta)) return fail(s, DGBGK_EINVAL, "theta must be > 0");
+  if (!(pb->tau > 0)) return fail(s, DGBGK_EINVAL, "tau must be > 0 (or +inf)");
+  for (int i = 0; i < pb->q; ++i)
+    if (!is_finite_d(pb->ex[i]) || !is_finite_d(pb->ey[i]) || !is_finite_d(pb->w[i]))
+      return fail(s, DGBGK_EINVAL, "velocity set entry %d is not finite", i);
+  for (int sd = 0; sd < 4; ++sd) {
+    if (pb->bc[sd] != DGBGK_BC_PERIODIC && pb->bc[sd] != DGBGK_BC_DIFFUSE_WALL)
+      return fail(s, DGBGK_EINVAL, "bc[%d] is not a dgbgk_bc", sd);
+    if (!is_finite_d(pb->wall_u[sd][0]) || !is_finite_d(pb->wall_u[sd][1]))
+      return fail(s, DGBGK_EINVAL, "wall_u[%d] is not finite", sd);
+  }
+  if ((pb->bc[0] == DGBGK_BC_PERIODIC) != (pb->bc[2] == DGBGK_BC_PERIODIC) ||
+      (pb->bc[1] == DGBGK_BC_PERIODIC) != (pb->bc[3] == DGBGK_BC_PERIODIC))
+    return fail(s, DGBGK_EINVAL, "periodic sides must come in pairs (0,2) and (1,3)");
+  // sides 0, 2 have normals along y; 1, 3 along x: the wall velocity must be tangential
+  for (int sd = 0; sd < 4; ++sd) {
+    if (pb->bc[sd] != DGBGK_BC_DIFFUSE_WALL) continue;
+    const double un = (sd % 2 == 0) ? pb->wall_u[sd][1] : pb->wall_u[sd][0];
+    if (un != 0.0) return fail(s, DGBGK_EINVAL, "wall_u[%d] has a normal component", sd);
+  }
+  return DGBGK_OK;
+}
+
+// Launch configuration: fused (all velocities of E elements per work-group)
+// when its LDS fits, else velocity tiles with a separate moments pass.
+void choose_tiling(dgbgk_solver *s) {
+  const int NP = s->Np;
+  const int G = kBlock / NP;
+  int E = 1;
+  while (E * 2 <= G && (int64_t)E * 2 * s->Q * NP <= 4096 && E * 2 <= s->K) E *= 2;
+  size_t lds = stage_lds_bytes(s->p, E, s->Q);
+  bool fused = lds <= kFusedLdsLimit;
+  if (s->tiling_mode == 1) fused = true;
+  if (s->tiling_mode == 2) fused = false;
+  if (fused) {
+    s->fused = 1;
+    s->Qt = s->Q;
+    s->ntiles = 1;
+  } else {
+    E = 1;
+    int qt = s->tiling_qt > 0 ? s->tiling_qt : s->Q;
+    if (qt > s->Q) qt = s->Q;
+    if (s->tiling_qt <= 0)
+      while (qt > 1 && stage_lds_bytes(s->p, E, qt) > kFusedLdsLimit) qt = (qt + 1) / 2;
+    s->fused = 0;
+    s->Qt = qt;
+    s->ntiles = (s->Q + qt - 1) / qt;
+    lds = stage_lds_bytes(s->p, E, qt);
+  }
+  s->E = E;
+  s->log2E = 0;
+  while ((1 << s->log2E) < E) ++s->log2E;
+  s->nblk = (int)((s->K + E - 1) / E);
+  s->lds = lds;
+}
+
+int ensure_device(dgbgk_solver *s) {
+  if (s->dev_ready) return DGBGK_OK;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(s, e, "hipGetDevice (no usable GPU)");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(s, e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(s, DGBGK_EDEVICE, "device %d is %s; this library is built for gfx950", dev,
+                prop.gcnArchName);
+  if (s->lds > prop.sharedMemPerBlock && s->lds > 65536)
+    return fail(s, DGBGK_EDEVICE, "stage kernel needs %zu B of LDS, device allows %zu", s->lds,
+                (size_t)prop.sharedMemPerBlock);
+  if (!s->base) {
+    void *p = nullptr;
+    e = hipMalloc(&p, s->lay.total);
+    if (e != hipSuccess) return fail(s, DGBGK_ENOMEM, "hipMalloc(%zu): %s", s->lay.total,
+                                     hipGetErrorString(e));
+    s->base = p;
+    s->owns = true;
+  }
+  char *b = (char *)s->base;
+  s->d_fn = (double *)(b + s->lay.fn);
+  s->d_acc = (double *)(b + s->lay.acc);
+  s->d_a = (double *)(b + s->lay.a);
+  s->d_b = (double *)(b + s->lay.b);
+  s->d_vel = (double *)(b + s->lay.vel);
+  s->d_feqb = (double *)(b + s->lay.feqb);
+  s->d_mom = (double *)(b + s->lay.mom);
+  s->d_rhow = (double *)(b + s->lay.rhow);
+  s->d_u64 = (unsigned long long *)(b + s->lay.u64);
+  std::vector<double> vel((size_t)3 * s->Q);
+  for (int q = 0; q < s->Q; ++q) {
+    vel[q] = s->ex[q];
+    vel[s->Q + q] = s->ey[q];
+    vel[2 * s->Q + q] = s->w[q];
+  }
+  e = hipMemcpyAsync(s->d_vel, vel.data(), vel.size() * sizeof(double), hipMemcpyHostToDevice,
+                     s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_feqb, s->feqb.data(), s->feqb.size() * sizeof(double),
+                       hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "uploading tables");
+  s->dev_ready = true;
+  return DGBGK_OK;
+}
+
+StageArgs base_args(const dgbgk_solver *s) {
+  StageArgs a;
+  std::memset(&a, 0, sizeof a);
+  const int N1 = s->p + 1;
+  for (int i = 0; i < N1 * N1; ++i) a.D1[i] = s->D1[i];
+  for (int i = 0; i < N1; ++i) {
+    a.lift_lo[i] = s->lift_lo[i];
+    a.lift_hi[i] = s->lift_hi[i];
+  }
+  a.vel = s->d_vel;
+  a.feqb = s->d_feqb;
+  a.mom = s->d_mom;
+  a.rhow = s->d_rhow;
+  a.rx = 2.0 / s->hx;
+  a.sy = 2.0 / s->hy;
+  a.fsx = 2.0 / s->hx;  // face Jacobian hy/2 over volume Jacobian hx hy/4
+  a.fsy = 2.0 / s->hy;
+  a.theta_inv = 1.0 / s->pb.theta;
+  a.half_theta2_inv = 1.0 / (2.0 * s->pb.theta * s->pb.theta);
+  a.half_theta_inv = 1.0 / (2.0 * s->pb.theta);
+  a.inv_tau = std::isinf(s->pb.tau) ? 0.0 : 1.0 / s->pb.tau;
+  for (int sd = 0; sd < 4; ++sd) a.wall_den_inv[sd] = s->wall_den_inv[sd];
+  a.nx = s->pb.nx;
+  a.ny = s->pb.ny;
+  a.K = (int)s->K;
+  a.Q = s->Q;
+  a.E = s->E;
+  a.log2E = s->log2E;
+  a.Qt = s->Qt;
+  a.nblk = s->nblk;
+  a.wall_mask = s->wall_mask;
+  a.periodic_x = s->pb.bc[1] == DGBGK_BC_PERIODIC;
+  a.periodic_y = s->pb.bc[0] == DGBGK_BC_PERIODIC;
+  a.fused = s->fused;
+  return a;
+}
+
+// One stage: L(fs) combined into the RK4 registers (stage 1..4) or written to
+// out (stage 0).  Tiled mode first reduces the moments of fs.
+int run_stage(dgbgk_solver *s, int stage, const double *fs, double *out, double dt,
+              double *rhow_out = nullptr) {
+  hipError_t e;
+  if (!s->fused) {
+    e = launch_moments(fs, s->d_vel, (int)s->K, s->p, s->Q, s->pb.nx, s->pb.ny, s->wall_mask,
+                       s->wall_den_inv, s->d_mom, s->d_mom + s->K * s->Np,
+                       s->d_mom + 2 * s->K * s->Np, s->wall_mask ? s->d_rhow : nullptr, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "moments kernel");
+  }
+  StageArgs a = base_args(s);
+  a.fs = fs;
+  a.fn = s->d_fn;
+  a.acc = s->d_acc;
+  a.out = out;
+  a.stage = stage;
+  a.rhow_out = rhow_out;
+  switch (stage) {
+    case 1: a.c_acc = dt / 6.0; a.c_out = dt / 2.0; break;
+    case 2: a.c_acc = dt / 3.0; a.c_out = dt / 2.0; break;
+    case 3: a.c_acc = dt / 3.0; a.c_out = dt; break;
+    case 4: a.c_acc = dt / 6.0; a.c_out = 0.0; break;
+    default: break;
+  }
+  e = launch_stage(s->p, a, s->lds, s->ntiles, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "stage kernel");
+  return DGBGK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dgbgk_version(void) { return "dgbgk 0.1 (gfx950, FP64)"; }
+
+const char *dgbgk_last_error(const dgbgk_solver *s) {
+  if (!s) return g_create_error.c_str();
+  return s->err.c_str();
+}
+
+int dgbgk_velset_gh(int32_t n1d, double *ex, double *ey, double *w, double *theta) {
+  if (!ex || !ey || !w) return fail(nullptr, DGBGK_EINVAL, "NULL output");
+  std::vector<double> x, wt;
+  if (!gauss_hermite_rule(n1d, x, wt)) return fail(nullptr, DGBGK_EINVAL, "n1d must be 1..40");
+  for (int b = 0; b < n1d; ++b)
+    for (int a = 0; a < n1d; ++a) {
+      ex[a + n1d * b] = x[a];
+      ey[a + n1d * b] = x[b];
+      w[a + n1d * b] = wt[a] * wt[b];
+    }
+  if (theta) *theta = 1.0;
+  return DGBGK_OK;
+}
+
+int dgbgk_velset_nc(int32_t m1d, double vmax, double *ex, double *ey, double *w, double *theta) {
+  if (!ex || !ey || !w) return fail(nullptr, DGBGK_EINVAL, "NULL output");
+  std::vector<double> x, wt;
+  if (!newton_cotes_rule(m1d, vmax, x, wt))
+    return fail(nullptr, DGBGK_EINVAL, "m1d must be 2..64 and vmax > 0");
+  double th = 0.0;
+  for (int b = 0; b < m1d; ++b)
+    for (int a = 0; a < m1d; ++a) {
+      const int q = a + m1d * b;
+      ex[q] = x[a];
+      ey[q] = x[b];
+      w[q] = wt[a] * wt[b];
+    }
+  for (int q = 0; q < m1d * m1d; ++q) th += w[q] * ex[q] * ex[q];
+  if (theta) *theta = th;
+  return DGBGK_OK;
+}
+
+int dgbgk_tau_from_kn(double kn, double L, int32_t convention, double *tau) {
+  if (!tau || !(kn > 0) || !(L > 0)) return fail(nullptr, DGBGK_EINVAL, "kn, L must be > 0");
+  if (convention == 0) *tau = kn * L / std::sqrt(3.0);
+  else if (convention == 1) *tau = kn * L / std::sqrt(M_PI / 2.0);
+  else return fail(nullptr, DGBGK_EINVAL, "convention must be 0 or 1");
+  return DGBGK_OK;
+}
+
+int dgbgk_required_bytes(const dgbgk_problem *pb, int32_t precision, size_t *bytes) {
+  if (!bytes) return fail(nullptr, DGBGK_EINVAL, "bytes is NULL");
+  int rc = validate(pb, nullptr);
+  if (rc) return rc;
+  if (precision != DGBGK_FP64) return fail(nullptr, DGBGK_ENOTSUP, "only DGBGK_FP64 is built");
+  const int N1 = pb->p + 1;
+  *bytes = make_layout((int64_t)pb->nx * pb->ny, N1 * N1, N1, pb->q).total;
+  return DGBGK_OK;
+}
+
+int dgbgk_create(const dgbgk_problem *pb, int32_t precision, void *hip_stream,
+                 dgbgk_solver **out) {
+  if (!out) return fail(nullptr, DGBGK_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(pb, nullptr);
+  if (rc) return rc;
+  if (precision != DGBGK_FP64) return fail(nullptr, DGBGK_ENOTSUP, "only DGBGK_FP64 is built");
+  dgbgk_solver *s = new (std::nothrow) dgbgk_solver;
+  if (!s) return fail(nullptr, DGBGK_ENOMEM, "out of host memory");
+  s->pb = *pb;
+  s->Q = pb->q;
+  s->ex.assign(pb->ex, pb->ex + pb->q);
+  s->ey.assign(pb->ey, pb->ey + pb->q);
+  s->w.assign(pb->w, pb->w + pb->q);
+  s->pb.ex = s->ex.data();
+  s->pb.ey = s->ey.data();
+  s->pb.w = s->w.data();
+  s->p = pb->p;
+  s->Nfp = pb->p + 1;
+  s->Np = s->Nfp * s->Nfp;
+  s->K = (int64_t)pb->nx * pb->ny;
+  s->hx = pb->lx / pb->nx;
+  s->hy = pb->ly / pb->ny;
+  s->stream = (hipStream_t)hip_stream;
+  // reference element
+  gll_points(s->p, s->r);
+  differentiation_matrix(s->r, s->D1);
+  mass_matrix(s->r, s->M1);
+  std::vector<double> e0(s->Nfp, 0.0), ep(s->Nfp, 0.0);
+  e0[0] = 1.0;
+  ep[s->p] = 1.0;
+  if (!spd_solve(s->Nfp, s->M1, e0, s->lift_lo) || !spd_solve(s->Nfp, s->M1, ep, s->lift_hi)) {
+    delete s;
+    return fail(nullptr, DGBGK_EINVAL, "mass matrix is not positive definite");
+  }
+  // walls: exterior equilibria f^eq(1, u_b) and the incoming-flux normalisation of eq. (8)
+  const double nrm[4][2] = {{0, -1}, {1, 0}, {0, 1}, {-1, 0}};
+  const double th = pb->theta;
+  s->feqb.assign((size_t)4 * s->Q, 0.0);
+  double umax = 0.0;
+  for (int sd = 0; sd < 4; ++sd) {
+    const double ubx = pb->wall_u[sd][0], uby = pb->wall_u[sd][1];
+    const double usq = ubx * ubx + uby * uby;
+    double den = 0.0;
+    for (int q = 0; q < s->Q; ++q) {
+      const double eu = s->ex[q] * ubx + s->ey[q] * uby;
+      const double fe = s->w[q] * (1.0 + eu / th + eu * eu / (2.0 * th * th) - usq / (2.0 * th));
+      s->feqb[(size_t)sd * s->Q + q] = fe;
+      const double cn = s->ex[q] * nrm[sd][0] + s->ey[q] * nrm[sd][1];
+      if (cn < 0.0) den += -cn * fe;
+    }
+    s->wall_den[sd] = den;
+    s->wall_den_inv[sd] = den > 0.0 ? 1.0 / den : 0.0;
+    if (pb->bc[sd] == DGBGK_BC_DIFFUSE_WALL) {
+      s->wall_mask |= 1 << sd;
+      if (!(den > 0.0)) {
+        delete s;
+        return fail(nullptr, DGBGK_EINVAL, "wall %d has no incoming velocity", sd);
+      }
+      umax = std::fmax(umax, std::sqrt(usq));
+    }
+  }
+  const double uref = umax > 0.0 ? umax : 1.0;
+  s->resid_scale = std::fmin(pb->lx, pb->ly) / uref;
+  s->lay = make_layout(s->K, s->Np, s->Nfp, s->Q);
+  choose_tiling(s);
+  *out = s;
+  return DGBGK_OK;
+}
+
+int dgbgk_bind_buffers(dgbgk_solver *s, void *device_ptr, size_t bytes) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (s->dev_ready || s->base) return fail(s, DGBGK_ESTATE, "device memory already in use");
+  if (!device_ptr) return fail(s, DGBGK_EINVAL, "device_ptr is NULL");
+  if ((uintptr_t)device_ptr % kAlign) return fail(s, DGBGK_EINVAL, "device_ptr must be 256-byte aligned");
+  if (bytes < s->lay.total)
+    return fail(s, DGBGK_EINVAL, "buffer of %zu B is smaller than the %zu B required", bytes,
+                s->lay.total);
+  s->base = device_ptr;
+  s->owns = false;
+  return ensure_device(s);
+}
+
+int dgbgk_set_stream(dgbgk_solver *s, void *hip_stream) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  s->stream = (hipStream_t)hip_stream;
+  return DGBGK_OK;
+}
+
+void dgbgk_destroy(dgbgk_solver *s) {
+  if (!s) return;
+  if (s->owns && s->base) {
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipFree(s->base);
+  }
+  delete s;
+}
+
+int dgbgk_sizes(const dgbgk_solver *s, int64_t *K, int32_t *Np, int32_t *Nfp, int32_t *Q) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (K) *K = s->K;
+  if (Np) *Np = s->Np;
+  if (Nfp) *Nfp = s->Nfp;
+  if (Q) *Q = s->Q;
+  return DGBGK_OK;
+}
+
+int dgbgk_stable_dt(const dgbgk_solver *s, double cfl, double *dt) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  dgbgk_solver *m = const_cast<dgbgk_solver *>(s);
+  if (!dt || !(cfl > 0) || !is_finite_d(cfl)) return fail(m, DGBGK_EINVAL, "cfl must be > 0");
+  double dr = 2.0;
+  for (int i = 0; i < s->p; ++i) dr = std::fmin(dr, s->r[i + 1] - s->r[i]);
+  double vmax = 0.0;
+  for (int q = 0; q < s->Q; ++q) vmax = std::fmax(vmax, std::fabs(s->ex[q]) + std::fabs(s->ey[q]));
+  if (!(vmax > 0)) return fail(m, DGBGK_EINVAL, "all velocities are zero");
+  *dt = cfl * (0.5 * std::fmin(s->hx, s->hy)) * dr / vmax;
+  return DGBGK_OK;
+}
+
+int dgbgk_node_coords(const dgbgk_solver *s, double *x, double *y) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (!x || !y) return fail(const_cast<dgbgk_solver *>(s), DGBGK_EINVAL, "NULL output");
+  const int N1 = s->Nfp;
+  for (int64_t k = 0; k < s->K; ++k) {
+    const int64_t kx = k % s->pb.nx, ky = k / s->pb.nx;
+    for (int n = 0; n < s->Np; ++n) {
+      const int i = n % N1, j = n / N1;
+      x[k * s->Np + n] = s->pb.x0 + s->hx * ((double)kx + 0.5 * (1.0 + s->r[i]));
+      y[k * s->Np + n] = s->pb.y0 + s->hy * ((double)ky + 0.5 * (1.0 + s->r[j]));
+    }
+  }
+  return DGBGK_OK;
+}
+
+int dgbgk_get_operator(const dgbgk_solver *s, int32_t which, double *out) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (!out) return fail(const_cast<dgbgk_solver *>(s), DGBGK_EINVAL, "NULL output");
+  const int N1 = s->Nfp, Np = s->Np, Nfp = s->Nfp;
+  switch (which) {
+    case 0:  // Dr = I (x) D1 acting on i
+    case 1:  // Ds = D1 (x) I acting on j
+      for (int a = 0; a < Np; ++a)
+        for (int b = 0; b < Np; ++b) {
+          const int ia = a % N1, ja = a / N1, ib = b % N1, jb = b / N1;
+          double v = 0.0;
+          if (which == 0 && ja == jb) v = s->D1[ia * N1 + ib];
+          if (which == 1 && ia == ib) v = s->D1[ja * N1 + jb];
+          out[a * Np + b] = v;
+        }
+      return DGBGK_OK;
+    case 2:
+      for (int a = 0; a < Np; ++a)
+        for (int b = 0; b < Np; ++b)
+          out[a * Np + b] = s->M1[(a % N1) * N1 + (b % N1)] * s->M1[(a / N1) * N1 + (b / N1)];
+      return DGBGK_OK;
+    case 3:
+      for (int a = 0; a < Np * 4 * Nfp; ++a) out[a] = 0.0;
+      for (int nd = 0; nd < Np; ++nd) {
+        const int i = nd % N1, j = nd / N1;
+        out[nd * 4 * Nfp + 0 * Nfp + i] = s->lift_lo[j];  // bottom face, node i of the face
+        out[nd * 4 * Nfp + 1 * Nfp + j] = s->lift_hi[i];  // right face
+        out[nd * 4 * Nfp + 2 * Nfp + i] = s->lift_hi[j];  // top face
+        out[nd * 4 * Nfp + 3 * Nfp + j] = s->lift_lo[i];  // left face
+      }
+      return DGBGK_OK;
+    case 4: std::memcpy(out, s->r.data(), sizeof(double) * N1); return DGBGK_OK;
+    case 5: std::memcpy(out, s->M1.data(), sizeof(double) * N1 * N1); return DGBGK_OK;
+    case 6:
+      out[0] = 2.0 / s->hy; out[1] = 2.0 / s->hx; out[2] = 2.0 / s->hy; out[3] = 2.0 / s->hx;
+      return DGBGK_OK;
+    case 7: std::memcpy(out, s->D1.data(), sizeof(double) * N1 * N1); return DGBGK_OK;
+    default: return fail(const_cast<dgbgk_solver *>(s), DGBGK_EINVAL, "unknown operator %d", which);
+  }
+}
+
+int dgbgk_init_equilibrium(dgbgk_solver *s, double rho0, double ux0, double uy0) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (!(rho0 > 0) || !is_finite_d(rho0) || !is_finite_d(ux0) || !is_finite_d(uy0))
+    return fail(s, DGBGK_EINVAL, "rho0 must be > 0 and u0 finite");
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  hipError_t e = launch_init_equilibrium(s->d_fn, s->d_vel, (int)s->K, s->Np, s->Q, rho0, ux0, uy0,
+                                         s->pb.theta, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "init kernel");
+  s->have_state = true;
+  s->steps = 0;
+  return DGBGK_OK;
+}
+
+int dgbgk_set_state(dgbgk_solver *s, const double *f, size_t count) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  const size_t need = (size_t)s->K * s->Np * s->Q;
+  if (!f || count != need) return fail(s, DGBGK_EINVAL, "state needs %zu doubles", need);
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(s->d_fn, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "set_state copy");
+  s->have_state = true;
+  s->steps = 0;
+  return DGBGK_OK;
+}
+
+int dgbgk_get_state(dgbgk_solver *s, double *f, size_t count) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  const size_t need = (size_t)s->K * s->Np * s->Q;
+  if (!f || count != need) return fail(s, DGBGK_EINVAL, "state needs %zu doubles", need);
+  if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
+  hipError_t e = hipMemcpyAsync(f, s->d_fn, need * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "get_state copy");
+  return DGBGK_OK;
+}
+
+int dgbgk_state_device_ptr(dgbgk_solver *s, void **ptr) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (!ptr) return fail(s, DGBGK_EINVAL, "ptr is NULL");
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  *ptr = s->d_fn;
+  return DGBGK_OK;
+}
+
+int dgbgk_step(dgbgk_solver *s, int64_t nsteps, double dt) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (nsteps < 0 || !(dt > 0) || !is_finite_d(dt)) return fail(s, DGBGK_EINVAL, "need nsteps >= 0, dt > 0");
+  if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  for (int64_t it = 0; it < nsteps; ++it) {
+    // registers: f_n, acc, and two stage buffers A/B so that a stage never
+    // overwrites the state its neighbours still read.
+    if ((rc = run_stage(s, 1, s->d_fn, s->d_a, dt))) return rc;
+    if ((rc = run_stage(s, 2, s->d_a, s->d_b, dt))) return rc;
+    if ((rc = run_stage(s, 3, s->d_b, s->d_a, dt))) return rc;
+    if ((rc = run_stage(s, 4, s->d_a, s->d_fn, dt))) return rc;
+    ++s->steps;
+  }
+  return DGBGK_OK;
+}
+
+int dgbgk_rhs(dgbgk_solver *s, const double *f, double *k, size_t count) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  const size_t need = (size_t)s->K * s->Np * s->Q;
+  if (!f || !k || count != need) return fail(s, DGBGK_EINVAL, "arrays need %zu doubles", need);
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(s->d_a, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "rhs input copy");
+  if ((rc = run_stage(s, 0, s->d_a, s->d_b, 0.0))) return rc;
+  e = hipMemcpyAsync(k, s->d_b, need * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "rhs output copy");
+  return DGBGK_OK;
+}
+
+int dgbgk_wall_density(dgbgk_solver *s, const double *f, double *out, size_t count) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  const size_t need = (size_t)s->K * s->Np * s->Q;
+  const size_t nout = (size_t)s->K * 4 * s->Nfp;
+  if (!f || !out || count != need) return fail(s, DGBGK_EINVAL, "state needs %zu doubles", need);
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(s->d_a, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "wall_density input copy");
+  e = launch_fill_u64((unsigned long long *)s->d_rhow, nout, 0ull, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "fill kernel");
+  if ((rc = run_stage(s, 0, s->d_a, s->d_b, 0.0, s->fused ? s->d_rhow : nullptr))) return rc;
+  e = hipMemcpyAsync(out, s->d_rhow, nout * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "wall_density output copy");
+  return DGBGK_OK;
+}
+
+static int residual_enqueue(dgbgk_solver *s) {
+  int rc = run_stage(s, 0, s->d_fn, s->d_b, 0.0);
+  if (rc) return rc;
+  hipError_t e = launch_fill_u64(s->d_u64, 1, 0ull, s->stream);
+  if (e == hipSuccess)
+    e = launch_residual(s->d_b, s->d_vel, (int)s->K, s->Np, s->Q, s->resid_scale, s->d_u64,
+                        s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "residual kernel");
+  return DGBGK_OK;
+}
+
+int dgbgk_residual(dgbgk_solver *s, double *r) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (!r) return fail(s, DGBGK_EINVAL, "r is NULL");
+  if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
+  int rc = residual_enqueue(s);
+  if (rc) return rc;
+  unsigned long long bits = 0;
+  hipError_t e = hipMemcpyAsync(&bits, s->d_u64, sizeof bits, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "residual copy");
+  double v;
+  std::memcpy(&v, &bits, sizeof v);
+  *r = v;
+  if (!std::isfinite(v)) {
+    *r = NAN;
+    return fail(s, DGBGK_ENONFINITE, "residual is not finite");
+  }
+  return DGBGK_OK;
+}
+
+int dgbgk_residual_async(dgbgk_solver *s, double *device_out) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (!device_out) return fail(s, DGBGK_EINVAL, "device_out is NULL");
+  if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
+  int rc = residual_enqueue(s);
+  if (rc) return rc;
+  hipError_t e = launch_u64_to_f64(s->d_u64, device_out, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "residual convert kernel");
+  return DGBGK_OK;
+}
+
+int dgbgk_moments(dgbgk_solver *s, double *rho, double *ux, double *uy) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (!rho || !ux || !uy) return fail(s, DGBGK_EINVAL, "NULL output");
+  if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
+  const size_t KN = (size_t)s->K * s->Np;
+  hipError_t e = launch_moments(s->d_fn, s->d_vel, (int)s->K, s->p, s->Q, s->pb.nx, s->pb.ny, 0,
+                                s->wall_den_inv, s->d_mom, s->d_mom + KN, s->d_mom + 2 * KN, nullptr,
+                                s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(rho, s->d_mom, KN * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(ux, s->d_mom + KN, KN * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(uy, s->d_mom + 2 * KN, KN * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "moments");
+  for (size_t i = 0; i < KN; ++i)
+    if (!std::isfinite(rho[i]) || !std::isfinite(ux[i]) || !std::isfinite(uy[i]))
+      return fail(s, DGBGK_ENONFINITE, "moment at node %zu is not finite", i);
+  return DGBGK_OK;
+}
+
+int dgbgk_synchronize(dgbgk_solver *s) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (!s->dev_ready) return DGBGK_OK;
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "synchronize");
+  return DGBGK_OK;
+}
+
+int dgbgk_steps_taken(const dgbgk_solver *s, int64_t *steps) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (!steps) return fail(const_cast<dgbgk_solver *>(s), DGBGK_EINVAL, "steps is NULL");
+  *steps = s->steps;
+  return DGBGK_OK;
+}
+
+int dgbgk_set_tiling(dgbgk_solver *s, int32_t mode, int32_t velocities_per_tile) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (mode < 0 || mode > 2) return fail(s, DGBGK_EINVAL, "mode must be 0, 1 or 2");
+  if (velocities_per_tile < 0) return fail(s, DGBGK_EINVAL, "velocities_per_tile must be >= 0");
+  const int saved_mode = s->tiling_mode, saved_qt = s->tiling_qt;
+  s->tiling_mode = mode;
+  s->tiling_qt = velocities_per_tile;
+  choose_tiling(s);
+  if (s->fused && s->lds > 160 * 1024) {
+    s->tiling_mode = saved_mode;
+    s->tiling_qt = saved_qt;
+    choose_tiling(s);
+    return fail(s, DGBGK_EINVAL, "fused tile does not fit in LDS");
+  }
+  return DGBGK_OK;
+}
+
+int dgbgk_get_tiling(const dgbgk_solver *s, int32_t *fused, int32_t *elems_per_group,
+                     int32_t *velocities_per_tile, size_t *lds_bytes) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (fused) *fused = s->fused;
+  if (elems_per_group) *elems_per_group = s->E;
+  if (velocities_per_tile) *velocities_per_tile = s->Qt;
+  if (lds_bytes) *lds_bytes = s->lds;
+  return DGBGK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Device kernels of the DG-BGK library and their launch parameters.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace dgbgk {
+
+constexpr int kMaxP = 8;
+constexpr int kMaxN1 = kMaxP + 1;
+constexpr int kBlock = 256;  // threads per work-group of the stage kernel
+
+// Everything one launch of the fused RK-stage kernel needs.  Passed by value:
+// the reference-element tables ride in the kernel-argument segment.
+struct StageArgs {
+  const double *fs;    // stage input state f_s[q][k][n]
+  const double *fn;    // state at the start of the step f_n
+  double *acc;         // RK4 accumulator
+  double *out;         // stage output (f_{s+1}, f_{n+1}, or L(f_s) when stage 0)
+  const double *vel;   // [3][Q]: e_x, e_y, w
+  const double *feqb;  // [4][Q]: f^eq_q(1, u_b) of each side's wall velocity
+  const double *mom;   // [3][K*Np]: rho, ux, uy  (tiled mode only)
+  const double *rhow;  // [K][4][Nfp]: diffuse-wall densities (tiled mode only)
+  double *rhow_out;    // optional [K][4][Nfp] copy of the wall densities (fused mode)
+  double D1[kMaxN1 * kMaxN1];  // 1-D GLL differentiation matrix
+  double lift_lo[kMaxN1];      // M1^{-1} e_0: lift of a flux on the left / bottom face
+  double lift_hi[kMaxN1];      // M1^{-1} e_p: lift of a flux on the right / top face
+  double rx, sy;               // 2/hx, 2/hy (reference-to-physical derivative scale)
+  double fsx, fsy;             // face-to-volume Jacobian ratio of x-faces / y-faces
+  double theta_inv;            // 1/theta
+  double half_theta2_inv;      // 1/(2 theta^2)
+  double half_theta_inv;       // 1/(2 theta)
+  double inv_tau;              // 1/tau (0 for tau = +inf)
+  double wall_den_inv[4];      // 1 / sum_{e.n<0} |e.n| f^eq(1,u_b) per side
+  double c_acc, c_out;         // RK4 coefficients of this stage (times dt)
+  int nx, ny, K, Q;
+  int E, log2E;                // elements per work-group (power of two)
+  int Qt;                      // velocities per work-group
+  int nblk;                    // element blocks (grid x)
+  int stage;                   // 0: out = L(f_s); 1..4: classical RK4 stage
+  int wall_mask;               // bit s: side s is a diffuse wall
+  int periodic_x, periodic_y;
+  int fused;                   // 1: moments and wall densities computed in-block
+};
+
+// LDS bytes of the stage kernel for (p, E, Qt).
+size_t stage_lds_bytes(int p, int E, int Qt);
+
+hipError_t launch_stage(int p, const StageArgs &a, size_t lds_bytes, int ntiles,
+                        hipStream_t stream);
+
+// rho, ux, uy of f at every node (any output may be null) and, when rhow is
+// non-null, the diffuse-wall densities of every wall face node.
+hipError_t launch_moments(const double *f, const double *vel, int K, int p, int Q, int nx,
+                          int ny, int wall_mask, const double *wall_den_inv4, double *rho,
+                          double *ux, double *uy, double *rhow, hipStream_t stream);
+
+// Scaled max-norm of the moment rates of k = L(f): atomically max-reduced into
+// *result (bit pattern of a non-negative double; must be zeroed first).
+hipError_t launch_residual(const double *k, const double *vel, int K, int Np, int Q,
+                           double scale, unsigned long long *result, hipStream_t stream);
+
+// f_q = f_q^eq(rho0, u0) everywhere.
+hipError_t launch_init_equilibrium(double *f, const double *vel, int K, int Np, int Q,
+                                   double rho0, double ux0, double uy0, double theta,
+                                   hipStream_t stream);
+
+hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v,
+                           hipStream_t stream);
+
+hipError_t launch_u64_to_f64(const unsigned long long *src, double *dst, hipStream_t stream);
+
+}  // namespace dgbgk

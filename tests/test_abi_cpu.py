@@ -1,0 +1,133 @@
+"""CPU-side checks of the C ABI: the library loads and exports every function
+declared in include/dgbgk.h; host-only calls (velocity sets, reference
+element, mesh, time step) agree with the oracle; argument errors are
+reported; device calls without a GPU fail loudly instead of falling back."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+from paper_2012_13487_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "dgbgk.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dgbgk_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = binding.lib()
+    names = _header_functions()
+    assert len(names) >= 25
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in binding.SIGNATURES, f"binding lacks {name}"
+    assert binding.version().startswith("dgbgk")
+
+
+@pytest.mark.parametrize("spec", [("gh", 4), ("gh", 3), ("gh", 9), ("gh", 18),
+                                  ("nc", 16, 4.0), ("nc", 24, 4.0), ("nc", 33, 4.0)])
+def test_velocity_sets_match_oracle(oracle_mod, spec):
+    a = binding.velocity_set(spec)
+    b = oracle_mod.velocity_set(spec)
+    assert np.max(np.abs(a[0] - b[0])) < 1e-14 * max(1.0, np.max(np.abs(b[0])))
+    assert np.max(np.abs(a[1] - b[1])) < 1e-14 * max(1.0, np.max(np.abs(b[1])))
+    assert np.max(np.abs(a[2] - b[2]) / b[2]) < 1e-12
+    assert abs(a[3] - b[3]) < 1e-15
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 8])
+def test_reference_element_matches_oracle(oracle_mod, p):
+    spec = workloads.couette(nx=3, ny=2, p=p)
+    s = binding.Solver.from_spec(spec)
+    o = oracle_mod.Oracle.from_spec(spec)
+    for which in range(7):
+        a, b = s.operator(which), o.operator(which)
+        assert np.max(np.abs(a - b)) < 2e-14 * max(1.0, np.max(np.abs(b))) * (p + 1), which
+    xs, ys = s.node_coords()
+    xo, yo = o.node_coords()
+    assert np.max(np.abs(xs - xo)) < 1e-15 and np.max(np.abs(ys - yo)) < 1e-15
+    assert s.stable_dt(0.2) == pytest.approx(o.stable_dt(0.2), rel=1e-14)
+    assert s.tau == pytest.approx(o.tau, rel=1e-15)
+
+
+def test_tiling_choice():
+    s = binding.Solver.from_spec(workloads.CAVITY_64x64_P3_NC16)
+    t = s.tiling()
+    assert t["fused"] and t["elems_per_group"] == 1 and t["velocities_per_tile"] == 256
+    big = binding.Solver.from_spec(workloads.CAVITY_128x128_P4_NC24_KN8)
+    t = big.tiling()
+    assert not t["fused"] and t["lds_bytes"] <= 64 * 1024
+    s.set_tiling(2, 48)
+    assert s.tiling() == {"fused": False, "elems_per_group": 1, "velocities_per_tile": 48,
+                          "lds_bytes": s.tiling()["lds_bytes"]}
+    s.set_tiling(0)
+    assert s.tiling()["fused"]
+
+
+def test_required_bytes():
+    spec = workloads.CAVITY_64x64_P3_NC16
+    vel = binding.velocity_set(spec.velset)
+    n = binding.required_bytes(spec.nx, spec.ny, spec.p, vel, 0.8, spec.bc, spec.wall_u)
+    assert n >= 4 * 16_777_216 * 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(p=0), dict(p=9), dict(tau=-1.0), dict(tau=0.0),
+    dict(bc=(0, 1, 1, 1)),                                   # unpaired periodic side
+    dict(wall_u=((0.0, 0.1), (0, 0), (0, 0), (0, 0))),        # normal wall velocity
+    dict(lx=-1.0), dict(bc=(2, 2, 2, 2)),
+])
+def test_create_rejects_invalid_problems(bad):
+    spec = workloads.cavity(n=2, p=1, m=4).with_(tau=0.5)
+    kw = dict(nx=spec.nx, ny=spec.ny, p=spec.p, velset=spec.velset, tau=spec.tau, bc=spec.bc,
+              wall_u=spec.wall_u, lx=spec.lx)
+    kw.update(bad)
+    with pytest.raises(binding.DgbgkError) as ei:
+        binding.Solver(**kw)
+    assert ei.value.code == binding.EINVAL
+
+
+def test_wall_without_incoming_velocity_is_rejected():
+    with pytest.raises(binding.DgbgkError):
+        binding.Solver(2, 2, 1, ("custom", [1.0], [0.0], [1.0], 1.0), 1.0,
+                       (1, 0, 1, 0), ((0, 0),) * 4)
+
+
+def test_bad_velocity_set_arguments():
+    with pytest.raises(binding.DgbgkError):
+        binding.velset_gh(0)
+    with pytest.raises(binding.DgbgkError):
+        binding.velset_nc(1, 4.0)
+    assert binding.tau_from_kn(1.0) == pytest.approx(1 / math.sqrt(math.pi / 2), rel=1e-15)
+    assert binding.tau_from_kn(1.0, 1.0, 0) == pytest.approx(1 / math.sqrt(3), rel=1e-15)
+
+
+def test_null_handle_is_einval():
+    L = binding.lib()
+    assert L.dgbgk_step(None, 1, 0.1) == binding.EINVAL
+    assert L.dgbgk_synchronize(None) == binding.EINVAL
+    assert L.dgbgk_last_error(None) is not None
+
+
+def test_device_calls_fail_loudly_without_gpu():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    s = binding.Solver.from_spec(workloads.couette(nx=2, ny=2, p=1))
+    with pytest.raises(binding.DgbgkError) as ei:
+        s.init_equilibrium()
+    assert ei.value.code == binding.EDEVICE
+    with pytest.raises(binding.DgbgkError) as ei:
+        s.step(1, 1e-3)
+    assert ei.value.code == binding.ESTATE

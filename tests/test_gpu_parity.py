@@ -1,0 +1,244 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs.  FP64 bar: 1e-12 relative in max-norm (right-hand
+side, wall densities, and rho, u after the same RK4 steps)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from paper_2012_13487_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _pair(oracle_mod, spec, tiling=None, **kw):
+    g = binding.Solver.from_spec(spec, **kw)
+    if tiling is not None:
+        g.set_tiling(*tiling)
+    o = oracle_mod.Oracle.from_spec(spec)
+    assert g.shape == o.shape
+    return g, o
+
+
+def _moment_errors(g, o):
+    rg, uxg, uyg = g.moments()
+    ro, uxo, uyo = o.moments()
+    u_g = np.stack([uxg, uyg])
+    u_o = np.stack([uxo, uyo])
+    return _rel(rg, ro), float(np.max(np.abs(u_g - u_o)) / max(np.max(np.abs(u_o)), 1e-300))
+
+
+RHS_CASES = [
+    ("couette_8x8_p2_gh4", workloads.couette(nx=8, ny=8, p=2), None),
+    ("cavity_6x5_p3_nc8", workloads.cavity(n=6, ny=5, p=3, m=8, lid=0.1), None),
+    ("cavity_5x3_p4_nc6_tiled", workloads.cavity(n=5, ny=3, p=4, m=6, lid=0.2), (2, 7)),
+    ("periodic_7x3_p1_gh3", workloads.periodic_box(nx=7, ny=3, p=1, velset=("gh", 3), kn=0.3), None),
+    ("periodic_1x1_p2_gh4", workloads.periodic_box(nx=1, ny=1, p=2, velset=("gh", 4)), None),
+    ("couette_3x1_p5_gh4", workloads.couette(nx=3, ny=1, p=5), None),
+    ("cavity_2x2_p8_nc4", workloads.cavity(n=2, p=8, m=4), None),
+    ("cavity_9x7_p3_nc9_oddQ", workloads.cavity(n=9, ny=7, p=3, m=9, lid=0.15), None),
+    ("cavity_9x7_p3_nc9_tiled", workloads.cavity(n=9, ny=7, p=3, m=9, lid=0.15), (2, 10)),
+    ("collisionless_4x4_p3", workloads.periodic_box(nx=4, ny=4, p=3, tau=float("inf")), None),
+]
+
+
+@pytest.mark.parametrize("name,spec,tiling", RHS_CASES, ids=[c[0] for c in RHS_CASES])
+def test_rhs_parity(oracle_mod, name, spec, tiling):
+    _say(f"[gpu] rhs parity {name}")
+    g, o = _pair(oracle_mod, spec, tiling)
+    f = workloads.perturbed_state(17, o.w, o.K, o.Np, amp=0.2)
+    kg = g.rhs(f)
+    ko = o.rhs(f)
+    assert np.isfinite(kg).all()
+    assert _rel(kg, ko) < TOL, (name, _rel(kg, ko))
+
+
+@pytest.mark.parametrize("name,spec,tiling", RHS_CASES[:4] + RHS_CASES[7:9],
+                         ids=[c[0] for c in RHS_CASES[:4] + RHS_CASES[7:9]])
+def test_wall_density_parity(oracle_mod, name, spec, tiling):
+    _say(f"[gpu] wall density parity {name}")
+    g, o = _pair(oracle_mod, spec, tiling)
+    f = workloads.perturbed_state(5, o.w, o.K, o.Np, amp=0.2)
+    wg = g.wall_density(f)
+    wo = o.wall_density(f)
+    wall = o.operator(7).astype(int) < 0
+    if wall.any():
+        assert _rel(wg[wall], wo[wall]) < TOL
+    assert np.all(wg[~wall] == 0.0)
+
+
+def test_couette_200_steps_matches_oracle(oracle_mod):
+    """Couette 8x8, p=2, D2Q16, Kn=1 (tau = Kn/sqrt(pi/2)), CFL 0.2, 200 steps."""
+    _say("[gpu] couette 8x8 p2 200 steps")
+    spec = workloads.COUETTE_8x8_P2_D2Q16
+    g, o = _pair(oracle_mod, spec)
+    dt = o.stable_dt(spec.cfl)
+    assert g.stable_dt(spec.cfl) == pytest.approx(dt, rel=1e-15)
+    g.init_equilibrium()
+    o.init_equilibrium()
+    g.step(spec.steps, dt)
+    o.rk4(spec.steps, dt)
+    er, eu = _moment_errors(g, o)
+    assert er < TOL and eu < TOL, (er, eu)
+    rho, ux, uy = g.moments()
+    assert np.max(np.abs(rho - 1)) < 1e-13 and np.max(np.abs(uy)) < 1e-14
+    assert g.steps_taken() == spec.steps
+
+
+@pytest.mark.parametrize("tiling", [None, (2, 13)])
+def test_cavity_perturbed_steps_match_oracle(oracle_mod, tiling):
+    _say(f"[gpu] cavity 10x7 p3 nc10 perturbed, tiling={tiling}")
+    spec = workloads.cavity(n=10, ny=7, p=3, m=10, lid=0.1, kn=0.5)
+    g, o = _pair(oracle_mod, spec, tiling)
+    f = workloads.perturbed_state(23, o.w, o.K, o.Np, amp=0.05)
+    g.set_state(f)
+    o.set_state(f)
+    dt = o.stable_dt(0.2)
+    g.step(40, dt)
+    o.rk4(40, dt)
+    er, eu = _moment_errors(g, o)
+    assert er < TOL and eu < TOL, (er, eu)
+    assert _rel(g.get_state(), o.get_state()) < TOL
+
+
+def test_fused_and_tiled_agree():
+    _say("[gpu] fused vs tiled")
+    spec = workloads.cavity(n=8, p=3, m=12, lid=0.1)
+    a = binding.Solver.from_spec(spec)
+    b = binding.Solver.from_spec(spec)
+    b.set_tiling(2, 40)
+    assert a.tiling()["fused"] and not b.tiling()["fused"]
+    for s in (a, b):
+        s.init_equilibrium()
+        s.step(30, s.stable_dt(0.2))
+    assert _rel(b.get_state(), a.get_state()) < 1e-13
+
+
+def test_residual_and_moments_parity(oracle_mod):
+    _say("[gpu] residual parity")
+    spec = workloads.cavity(n=6, p=2, m=8, lid=0.1)
+    g, o = _pair(oracle_mod, spec)
+    f = workloads.perturbed_state(3, o.w, o.K, o.Np, amp=0.1)
+    g.set_state(f)
+    o.set_state(f)
+    rg = g.residual()
+    ro, rc = o.residual()
+    assert rc == 0 and abs(rg - ro) < 1e-12 * ro
+    er, eu = _moment_errors(g, o)
+    assert er < 1e-14 and eu < 1e-14
+    # at rest with the lid stopped the state is a fixed point
+    g2 = binding.Solver.from_spec(spec.with_(wall_u=((0, 0),) * 4))
+    g2.init_equilibrium()
+    assert g2.residual() < 1e-12
+
+
+def test_residual_async_and_nonfinite():
+    _say("[gpu] residual async / nonfinite")
+    import torch
+    spec = workloads.cavity(n=4, p=2, m=6)
+    g = binding.Solver.from_spec(spec, stream="torch", torch_memory=True)
+    g.init_equilibrium()
+    g.step(5, g.stable_dt(0.2))
+    out = torch.full((1,), -1.0, dtype=torch.float64, device="cuda")
+    g.residual_async(out.data_ptr())
+    torch.cuda.current_stream().synchronize()
+    assert out.item() == pytest.approx(g.residual(), rel=0, abs=0)
+    f = g.get_state()
+    f[2, 3, 1] = np.nan
+    g.set_state(f)
+    with pytest.raises(binding.DgbgkError) as ei:
+        g.residual()
+    assert ei.value.code == binding.ENONFINITE
+    with pytest.raises(binding.DgbgkError) as ei:
+        g.moments()
+    assert ei.value.code == binding.ENONFINITE
+
+
+def test_mass_conservation_on_gpu():
+    _say("[gpu] mass conservation")
+    spec = workloads.cavity(n=8, p=3, m=10, lid=0.1, kn=0.5)
+    g = binding.Solver.from_spec(spec)
+    M = np.kron(g.operator(5), g.operator(5))  # tensor mass matrix (host table)
+    J = (1 / 8) ** 2 / 4
+    f = workloads.perturbed_state(8, g.w, g.K, g.Np, amp=0.1)
+    g.set_state(f)
+    m0 = J * np.einsum("n,kn->", M.sum(axis=0), g.moments()[0])
+    g.step(300, g.stable_dt(0.2))
+    m1 = J * np.einsum("n,kn->", M.sum(axis=0), g.moments()[0])
+    assert abs(m1 - m0) < 2e-14 * m0
+
+
+def test_determinism_and_checkpoint():
+    _say("[gpu] determinism / checkpoint")
+    spec = workloads.cavity(n=8, p=3, m=8, lid=0.1)
+    dt = None
+    outs = []
+    for _ in range(2):
+        g = binding.Solver.from_spec(spec)
+        dt = g.stable_dt(0.2)
+        g.init_equilibrium()
+        g.step(60, dt)
+        outs.append(g.get_state())
+    assert np.array_equal(outs[0], outs[1])
+    g = binding.Solver.from_spec(spec)
+    g.init_equilibrium()
+    g.step(30, dt)
+    mid = g.get_state()
+    h = binding.Solver.from_spec(spec)
+    h.set_state(mid)
+    h.step(30, dt)
+    assert np.array_equal(h.get_state(), outs[0])
+
+
+def test_errors_on_device():
+    _say("[gpu] error paths")
+    g = binding.Solver.from_spec(workloads.cavity(n=3, p=1, m=4))
+    with pytest.raises(binding.DgbgkError) as ei:
+        g.step(1, 1e-3)
+    assert ei.value.code == binding.ESTATE
+    with pytest.raises(binding.DgbgkError) as ei:
+        g.set_state(np.zeros(5))
+    assert ei.value.code == binding.EINVAL
+    g.init_equilibrium()
+    with pytest.raises(binding.DgbgkError) as ei:
+        g.step(1, -1.0)
+    assert ei.value.code == binding.EINVAL
+    # an unstable step diverges and is reported as non-finite, not hidden
+    g.step(400, 50 * g.stable_dt(1.0))
+    with pytest.raises(binding.DgbgkError) as ei:
+        g.residual()
+    assert ei.value.code == binding.ENONFINITE
+
+
+def test_full_size_cavity_64x64_p3_nc16_matches_oracle(oracle_mod):
+    """The benchmark workload at full size (16.8 M DOF) in the launch
+    configuration the benchmark times: RHS of a perturbed state, and rho, u
+    after 2 RK4 steps, element by element against the oracle."""
+    _say("[gpu] full-size cavity 64x64 p3 nc16")
+    spec = workloads.CAVITY_64x64_P3_NC16
+    g, o = _pair(oracle_mod, spec, stream="torch", torch_memory=True)
+    assert g.tiling()["fused"]
+    f = workloads.perturbed_state(31, o.w, o.K, o.Np, amp=0.05)
+    _say("  rhs")
+    assert _rel(g.rhs(f), o.rhs(f)) < TOL
+    g.set_state(f)
+    o.set_state(f)
+    dt = o.stable_dt(spec.cfl)
+    _say("  2 steps")
+    g.step(2, dt)
+    o.rk4(2, dt)
+    er, eu = _moment_errors(g, o)
+    assert er < TOL and eu < TOL, (er, eu)
