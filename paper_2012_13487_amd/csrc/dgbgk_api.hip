@@ -27,7 +27,7 @@ constexpr int kMaxQ = 4096;
 size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t fn, acc, a, b, vel, feqb, mom, rhow, u64, total;
+  size_t fn, acc, a, b, vel, feqb, wmom, mom, rhow, u64, total;
 };
 
 Layout make_layout(int64_t K, int Np, int Nfp, int Q) {
@@ -40,6 +40,7 @@ Layout make_layout(int64_t K, int Np, int Nfp, int Q) {
   L.b = off;    off += round_up(dof);
   L.vel = off;  off += round_up((size_t)3 * Q * sizeof(double));
   L.feqb = off; off += round_up((size_t)4 * Q * sizeof(double));
+  L.wmom = off; off += round_up((size_t)16 * Q * sizeof(double));
   L.mom = off;  off += round_up((size_t)3 * K * Np * sizeof(double));
   L.rhow = off; off += round_up((size_t)K * 4 * Nfp * sizeof(double));
   L.u64 = off;  off += round_up(8 * sizeof(unsigned long long));
@@ -70,7 +71,7 @@ struct dgbgk_solver {
   bool owns = false;
   Layout lay{};
   double *d_fn = nullptr, *d_acc = nullptr, *d_a = nullptr, *d_b = nullptr;
-  double *d_vel = nullptr, *d_feqb = nullptr, *d_mom = nullptr, *d_rhow = nullptr;
+  double *d_vel = nullptr, *d_feqb = nullptr, *d_wmom = nullptr, *d_mom = nullptr, *d_rhow = nullptr;
   unsigned long long *d_u64 = nullptr;
   // launch configuration
   int fused = 1, E = 1, log2E = 0, Qt = 0, ntiles = 1, nblk = 1;
@@ -197,6 +198,7 @@ int ensure_device(dgbgk_solver *s) {
   s->d_b = (double *)(b + s->lay.b);
   s->d_vel = (double *)(b + s->lay.vel);
   s->d_feqb = (double *)(b + s->lay.feqb);
+  s->d_wmom = (double *)(b + s->lay.wmom);
   s->d_mom = (double *)(b + s->lay.mom);
   s->d_rhow = (double *)(b + s->lay.rhow);
   s->d_u64 = (unsigned long long *)(b + s->lay.u64);
@@ -206,8 +208,25 @@ int ensure_device(dgbgk_solver *s) {
     vel[s->Q + q] = s->ey[q];
     vel[2 * s->Q + q] = s->w[q];
   }
+  // moment weights per velocity: 1, e_x, e_y, then the outgoing normal speed
+  // e.n > 0 at a bottom, right, top and left wall (for eq. (8)); rest zero
+  std::vector<double> wm((size_t)16 * s->Q, 0.0);
+  for (int q = 0; q < s->Q; ++q) {
+    const double cx = s->ex[q], cy = s->ey[q];
+    double *r = &wm[(size_t)16 * q];
+    r[0] = 1.0;
+    r[1] = cx;
+    r[2] = cy;
+    r[3] = cy < 0.0 ? -cy : 0.0;
+    r[4] = cx > 0.0 ? cx : 0.0;
+    r[5] = cy > 0.0 ? cy : 0.0;
+    r[6] = cx < 0.0 ? -cx : 0.0;
+  }
   e = hipMemcpyAsync(s->d_vel, vel.data(), vel.size() * sizeof(double), hipMemcpyHostToDevice,
                      s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_wmom, wm.data(), wm.size() * sizeof(double), hipMemcpyHostToDevice,
+                       s->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(s->d_feqb, s->feqb.data(), s->feqb.size() * sizeof(double),
                        hipMemcpyHostToDevice, s->stream);
@@ -228,6 +247,7 @@ StageArgs base_args(const dgbgk_solver *s) {
   }
   a.vel = s->d_vel;
   a.feqb = s->d_feqb;
+  a.wmom = s->d_wmom;
   a.mom = s->d_mom;
   a.rhow = s->d_rhow;
   a.rx = 2.0 / s->hx;

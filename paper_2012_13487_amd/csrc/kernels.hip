@@ -3,54 +3,87 @@
 // The hot path is one fused kernel per RK4 stage.  A work-group owns a block
 // of E consecutive elements and a tile of Qt velocities (Qt = Q in fused
 // mode) and, in one pass over HBM:
-//   1. stages f_s[q][k][n] of its block in LDS (coalesced: consecutive lanes
-//      read consecutive nodes of one velocity row);
+//   1. stages f_s[q][k][n] of its block in LDS with coalesced 16-byte loads;
 //   2. reduces the node moments rho, rho u (Sec. II.A) over the velocities in
 //      LDS, and the diffuse-wall densities of eq. (8) at wall face nodes;
 //      in tiled mode both come from a separate moments pass instead;
-//   3. forms the upwind face jumps (e.n)(f^- - f^+) on inflow faces, with f^+
-//      the neighbour trace or the wall exterior state rho_w f^eq(1, u_b);
-//   4. per (velocity, node): volume term -e.grad f by the 1-D derivative
-//      matrix along the node's grid line (sum factorisation of Dr = I x D1,
-//      Ds = D1 x I), lift of the two inflow-face jumps (LIFT = M^{-1} E is a
-//      rank-one outer product per face on tensor GLL elements), BGK collision
-//      with the second-order equilibrium eq. (5), and the RK4 register update.
+//   3. per (velocity, element) row, in registers: the volume term -e.grad f
+//      by sum factorisation (Dr = I x D1, Ds = D1 x I, D1 uniform across the
+//      wavefront), the upwind jumps (e.n)(f^- - f^+) on the two inflow faces
+//      lifted by LIFT = M^{-1} E (a rank-one outer product per face on tensor
+//      GLL elements), with f^+ the neighbour trace or the wall exterior state
+//      rho_w f^eq(1, u_b), and the BGK collision with the second-order
+//      equilibrium eq. (5); L(f) goes back into the row in LDS;
+//   4. the classical RK4 register update, streaming f_n / acc / outputs with
+//      coalesced 16-byte accesses.
 // The path is HBM-bound (about 2.5-5 flop per byte in FP64), so the small
 // contractions run on the FP64 vector units from registers and LDS rather
 // than being padded out to matrix-core tiles.
 #include "kernels.hpp"
 
 #include <cmath>
+#include <type_traits>
 
 namespace dgbgk {
 
 namespace {
+
+typedef double double4v __attribute__((ext_vector_type(4)));
+typedef double double2v __attribute__((ext_vector_type(2)));  // native 16-byte vector
 
 template <int P>
 struct Shape {
   static constexpr int N1 = P + 1;
   static constexpr int NP = N1 * N1;
   static constexpr int NFP = N1;
-  static constexpr int S = (NP % 2 == 0) ? NP + 1 : NP;  // odd LDS row stride (doubles)
+  static constexpr int S = (NP % 2 == 0) ? NP + 2 : NP;
   static constexpr int G = kBlock / NP;                   // node groups per work-group
   static constexpr int T = G * NP;                        // threads with a node
+  static constexpr bool VEC = (NP % 2 == 0);              // 16-byte loads of f
 };
 
 struct LdsLayout {
-  int jump, mom, rw, total;  // offsets / size in doubles; the tile starts at 0
+  int part, mom, rw, nbr, total;  // offsets / size in doubles; the tile starts at 0
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int NP, int NFP, int S, int T, int E, int Qt) {
+__host__ __device__ inline LdsLayout lds_layout(int NP, int NFP, int S, int E, int Qt) {
   LdsLayout L;
   const int tile_sz = Qt * E * S;
-  int jump_sz = Qt * E * 2 * NFP;
-  const int part_sz = 7 * T;  // moment partials alias the jump buffer
-  if (part_sz > jump_sz) jump_sz = part_sz;
-  L.jump = tile_sz;
-  L.mom = L.jump + jump_sz;
+  const int tasks = E * ((NP + 15) / 16);
+  const int pairs = tasks >= 4 ? tasks : 4;  // (task, K slice) partial products
+  L.part = tile_sz;
+  L.mom = (L.part + pairs * 7 * 16 + 3) / 4 * 4;  // 32-byte aligned (read as double4)
   L.rw = L.mom + E * NP * 4;
-  L.total = L.rw + E * 4 * NFP;
+  L.nbr = L.rw + E * 4 * NFP;
+  L.total = L.nbr + (E * 4 + 1) / 2;  // E*4 ints
   return L;
+}
+
+// out / new accumulator of one RK4 stage from k = L(f_s):
+//   MODE 1: acc = f_s + dt/6 k, out = f_s + dt/2 k          (x = f_s)
+//   MODE 2: acc = acc + dt/3 k, out = f_n + c dt k, c = 1/2, 1  (x = f_n, y = acc)
+//   MODE 4: out = acc + dt/6 k                               (x = acc)
+//   MODE 0: out = k
+template <int MODE>
+__device__ inline double rk_one(double kv, double x, double y, double ca, double co, double &an) {
+  if (MODE == 0) return kv;
+  if (MODE == 1) { an = x + ca * kv; return x + co * kv; }
+  if (MODE == 2) { an = y + ca * kv; return x + co * kv; }
+  return x + ca * kv;
+}
+template <int MODE>
+__device__ inline void rk_update(double kv, double x, double y, double ca, double co, double &o,
+                                 double &an) {
+  o = rk_one<MODE>(kv, x, y, ca, co, an);
+}
+template <int MODE>
+__device__ inline void rk_update(const double2v &kv, const double2v &x, const double2v &y, double ca,
+                                 double co, double2v &o, double2v &an) {
+  double o0, o1, a0 = 0.0, a1 = 0.0;
+  o0 = rk_one<MODE>(kv[0], x[0], y[0], ca, co, a0);
+  o1 = rk_one<MODE>(kv[1], x[1], y[1], ca, co, a1);
+  o = double2v{o0, o1};
+  an = double2v{a0, a1};
 }
 
 // Work-groups are handed to the 8 XCDs round-robin; give each XCD a
@@ -59,6 +92,25 @@ __host__ __device__ inline LdsLayout lds_layout(int NP, int NFP, int S, int T, i
 __device__ inline int xcd_block(int b, int nblk) {
   const int per = nblk >> 3, rem = nblk & 7, x = b & 7;
   return x * per + (x < rem ? x : rem) + (b >> 3);
+}
+
+// LDS rows have an odd stride, so 16-byte values move as two 8-byte halves.
+__device__ __forceinline__ void lds_put(double *p, double v) { *p = v; }
+__device__ __forceinline__ void lds_put(double *p, const double2v &v) { *reinterpret_cast<double2v *>(p) = v; }
+template <typename V>
+__device__ __forceinline__ V lds_get(const double *p);
+template <>
+__device__ __forceinline__ double lds_get<double>(const double *p) { return *p; }
+template <>
+__device__ __forceinline__ double2v lds_get<double2v>(const double *p) { return *reinterpret_cast<const double2v *>(p); }
+
+// Access c of a block's f tile (CW doubles each, CPE per element and velocity):
+// velocity q, element e, access w within the velocity row.
+template <int CPE>
+__device__ __forceinline__ void split_access(int c, int cpr, int log2E, int &q, int &e, int &w) {
+  q = (c >> log2E) / CPE;
+  w = c - q * cpr;
+  e = w / CPE;
 }
 
 __device__ inline int neighbour(int k, int face, const StageArgs &a) {
@@ -71,100 +123,169 @@ __device__ inline int neighbour(int k, int face, const StageArgs &a) {
   }
 }
 
-template <int P>
+// MODE: 0 writes L(f_s); 1 first RK4 stage; 2 second and third; 4 fourth.
+template <int P, int MODE>
 __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
   using Sh = Shape<P>;
-  constexpr int N1 = Sh::N1, NP = Sh::NP, NFP = Sh::NFP, S = Sh::S, G = Sh::G, T = Sh::T;
+  constexpr int N1 = Sh::N1, NP = Sh::NP, NFP = Sh::NFP, S = Sh::S;
+  constexpr int CW = Sh::VEC ? 2 : 1;  // doubles per global access
+  constexpr int CPE = NP / CW;         // accesses per element per velocity
+  constexpr int U = 8;                 // global accesses in flight per thread
+  constexpr int NB = (NP + 15) / 16;   // 16-node column blocks of the moment product
+  using V = typename std::conditional<Sh::VEC, double2v, double>::type;
   extern __shared__ double lds[];
   const int E = a.E, log2E = a.log2E;
-  const LdsLayout L = lds_layout(NP, NFP, S, T, E, a.Qt);
+  const LdsLayout L = lds_layout(NP, NFP, S, E, a.Qt);
   double *tile = lds;
-  double *jump = lds + L.jump;
-  double *part = jump;
+  double *part = lds + L.part;
   double *mom = lds + L.mom;
   double *rw = lds + L.rw;
+  int *nbr = (int *)(lds + L.nbr);
 
   const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
   const int blk = xcd_block(blockIdx.x, a.nblk);
   const int k0 = blk * E;
   const int Eb = min(E, a.K - k0);
   const int q0 = blockIdx.y * a.Qt;
   const int Qb = min(a.Qt, a.Q - q0);
   const int rows = Qb * E;  // LDS row r = q_local * E + e
+  const int cpr = E * CPE;  // accesses per velocity row of the block
+  const int nch = Qb * cpr;
   const size_t KNP = (size_t)a.K * NP;
+  const size_t boff = (size_t)q0 * KNP + (size_t)k0 * NP;  // block origin in f
   const double *vex = a.vel;
   const double *vey = a.vel + a.Q;
   const double *vw = a.vel + 2 * a.Q;
 
-  const int n = tid % NP;  // each thread keeps one node for the whole kernel
-  const int g = tid / NP;
-  const bool active = tid < T;
+  // ---- 0. loads of this thread's first velocity row that do not depend on the
+  //         stage's arithmetic (velocity, weights, exterior traces): issued
+  //         first so that they are in flight during phases 1 and 2
+  const int r0 = tid;
+  double cx0 = 0.0, cy0 = 0.0, wq0 = 0.0, gbx0 = 0.0, gby0 = 0.0;
+  double px0[NFP], py0[NFP];
+  int nbx0 = -1, nby0 = -1;
+  if (r0 < rows && (r0 & (E - 1)) < Eb) {
+    const int q = r0 >> log2E, e = r0 & (E - 1), qg = q0 + q;
+    cx0 = vex[qg];
+    cy0 = vey[qg];
+    wq0 = vw[qg];
+    const int fxc = cx0 > 0.0 ? 3 : 1, fyc = cy0 > 0.0 ? 0 : 2;
+    nbx0 = neighbour(k0 + e, fxc, a);
+    nby0 = neighbour(k0 + e, fyc, a);
+    gbx0 = a.feqb[fxc * a.Q + qg];
+    gby0 = a.feqb[fyc * a.Q + qg];
+    const double *sx = a.fs + (size_t)qg * KNP + (size_t)(nbx0 >= 0 ? nbx0 : 0) * NP + (cx0 > 0.0 ? P : 0);
+    const double *sy = a.fs + (size_t)qg * KNP + (size_t)(nby0 >= 0 ? nby0 : 0) * NP + (cy0 > 0.0 ? N1 * P : 0);
+    const bool gx = cx0 != 0.0 && nbx0 >= 0, gy = cy0 != 0.0 && nby0 >= 0;
+#pragma unroll
+    for (int m = 0; m < NFP; ++m) {
+      px0[m] = gx ? sx[N1 * m] : 0.0;
+      py0[m] = gy ? sy[m] : 0.0;
+    }
+  }
 
-  // ---- 1. stage f_s of the block --------------------------------------------
-  if (active) {
-    for (int r = g; r < rows; r += G) {
-      const int q = r >> log2E, e = r & (E - 1);
-      if (e < Eb) tile[r * S + n] = a.fs[(size_t)(q0 + q) * KNP + (size_t)(k0 + e) * NP + n];
+  // ---- 0b. neighbours of the block's elements (-1: wall) -----------------------
+  if (tid < E * 4) {
+    const int e = tid >> 2, fc = tid & 3;
+    nbr[tid] = e < Eb ? neighbour(k0 + e, fc, a) : -1;
+  }
+
+  // ---- 1. f_s of the block into LDS (coalesced, U accesses in flight) ----------
+  const bool full = Eb == E;
+  {
+    const double *src = a.fs + boff;
+    for (int c0 = tid; c0 < nch; c0 += nthr * U) {
+      V v[U];
+      const bool all = full && c0 - tid + U * nthr <= nch;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * nthr;
+        int q, e, w;
+        split_access<CPE>(c, cpr, log2E, q, e, w);
+        if (all || (c < nch && e < Eb)) v[u] = *reinterpret_cast<const V *>(src + (size_t)q * KNP + CW * w);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * nthr;
+        int q, e, w;
+        split_access<CPE>(c, cpr, log2E, q, e, w);
+        if (all || (c < nch && e < Eb)) lds_put(tile + (q * E + e) * S + CW * (w - e * CPE), v[u]);
+      }
     }
   }
   __syncthreads();
 
   // ---- 2. node moments and diffuse-wall densities ----------------------------
+  // C[c][n] = sum_q W[q][c] f[q][n] with W[q] = (1, e_x, e_y, outgoing normal
+  // speed at the bottom, right, top, left wall): a dense (7 x Q) x (Q x NP)
+  // product per element, on FP64 matrix cores (16x16x4 steps; K split over
+  // the four wavefronts, partial products summed through LDS).
   const bool walls = a.wall_mask != 0;
   if (a.fused) {
-    const int Gp = G >> log2E;  // groups per (element, node)
-    const int e = g & (E - 1), gp = g >> log2E;
-    if (active && gp < Gp) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, hb = 0.0, hr = 0.0, ht = 0.0, hl = 0.0;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int tasks = E * NB;                     // (element, 16-node block)
+    const int ks = tasks >= 4 ? 1 : 4 / tasks;    // K slices per task
+    const int qper = ((Qb + ks - 1) / ks + 3) / 4 * 4;
+    for (int pr = wave; pr < tasks * ks; pr += nthr >> 6) {
+      const int t = pr / ks, sl = pr % ks;
+      const int e = t / NB, nb = t % NB;
+      const int node = nb * 16 + (lane & 15);
+      const int qa = sl * qper, qe = min(Qb, qa + qper);
+      double4v acc = {0.0, 0.0, 0.0, 0.0};
       if (e < Eb) {
-        for (int q = gp; q < Qb; q += Gp) {
-          const double v = tile[(q * E + e) * S + n];
-          const double cx = vex[q0 + q], cy = vey[q0 + q];
-          s0 += v;
-          s1 += cx * v;
-          s2 += cy * v;
-          if (walls) {  // outgoing (e.n > 0) flux per wall side
-            hb += cy < 0.0 ? -cy * v : 0.0;
-            hr += cx > 0.0 ? cx * v : 0.0;
-            ht += cy > 0.0 ? cy * v : 0.0;
-            hl += cx < 0.0 ? -cx * v : 0.0;
+        constexpr int KB = 16;  // 4-velocity steps whose operands are loaded together
+        for (int qb = qa; qb < qe; qb += 4 * KB) {
+          double av[KB], bv[KB];
+#pragma unroll
+          for (int t = 0; t < KB; ++t) {
+            const int q = qb + 4 * t + (lane >> 4);
+            const bool in = q < qe;
+            av[t] = in ? a.wmom[(size_t)(q0 + q) * 16 + (lane & 15)] : 0.0;
+            bv[t] = (in && node < NP) ? tile[(q * E + e) * S + node] : 0.0;
           }
+#pragma unroll
+          for (int t = 0; t < KB; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc, 0, 0, 0);
         }
       }
-      double *pp = part + ((gp * E + e) * NP + n) * 7;
-      pp[0] = s0; pp[1] = s1; pp[2] = s2;
-      pp[3] = hb; pp[4] = hr; pp[5] = ht; pp[6] = hl;
+      // register v of a lane holds C[4 v + lane / 16][lane % 16]; rows 0..6 are used
+      if (node < NP) {
+        double *pp = part + ((size_t)pr * 7) * 16;
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const int row = 4 * v + (lane >> 4);
+          if (row < 7) pp[row * 16 + (lane & 15)] = acc[v];
+        }
+      }
     }
     __syncthreads();
     if (tid < E * NP) {
       const int e2 = tid / NP, n2 = tid % NP;
       if (e2 < Eb) {
-        double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int gp2 = 0; gp2 < Gp; ++gp2) {
-          const double *pp = part + ((gp2 * E + e2) * NP + n2) * 7;
+        const int t = e2 * NB + n2 / 16, col = n2 % 16;
+        double sm[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int sl = 0; sl < ks; ++sl) {
+          const double *pp = part + ((size_t)(t * ks + sl) * 7) * 16;
 #pragma unroll
-          for (int c = 0; c < 7; ++c) s[c] += pp[c];
+          for (int c = 0; c < 7; ++c) sm[c] += pp[c * 16 + col];
         }
-        const double rho = s[0], ux = s[1] / rho, uy = s[2] / rho;
+        const double rho = sm[0], ux = sm[1] / rho, uy = sm[2] / rho;
         double *m = mom + (e2 * NP + n2) * 4;
         m[0] = ux;
         m[1] = uy;
         m[2] = rho;
         m[3] = 1.0 - (ux * ux + uy * uy) * a.half_theta_inv;
         if (walls) {
-          const int k = k0 + e2, kx = k % a.nx, ky = k / a.nx;
           const int i2 = n2 % N1, j2 = n2 / N1;
-          const bool on[4] = {(a.wall_mask & 1) && ky == 0 && j2 == 0,
-                              (a.wall_mask & 2) && kx == a.nx - 1 && i2 == P,
-                              (a.wall_mask & 4) && ky == a.ny - 1 && j2 == P,
-                              (a.wall_mask & 8) && kx == 0 && i2 == 0};
+          const bool on[4] = {nbr[e2 * 4 + 0] < 0 && j2 == 0, nbr[e2 * 4 + 1] < 0 && i2 == P,
+                              nbr[e2 * 4 + 2] < 0 && j2 == P, nbr[e2 * 4 + 3] < 0 && i2 == 0};
           const int fm[4] = {i2, j2, i2, j2};
 #pragma unroll
           for (int fc = 0; fc < 4; ++fc)
             if (on[fc]) {
-              const double v = s[3 + fc] * a.wall_den_inv[fc];
+              const double v = sm[3 + fc] * a.wall_den_inv[fc];
               rw[(e2 * 4 + fc) * NFP + fm[fc]] = v;
-              if (a.rhow_out) a.rhow_out[((size_t)k * 4 + fc) * NFP + fm[fc]] = v;
+              if (a.rhow_out) a.rhow_out[((size_t)(k0 + e2) * 4 + fc) * NFP + fm[fc]] = v;
             }
         }
       }
@@ -183,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
       }
     }
     if (walls) {
-      for (int u = tid; u < E * 4 * NFP; u += blockDim.x) {
+      for (int u = tid; u < E * 4 * NFP; u += nthr) {
         const int e2 = u / (4 * NFP);
         if (e2 < Eb) rw[u] = a.rhow[(size_t)(k0 + e2) * 4 * NFP + (u - e2 * 4 * NFP)];
       }
@@ -191,89 +312,148 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
   }
   __syncthreads();
 
-  // ---- 3. upwind jumps on the inflow faces -------------------------------------
-  for (int u = tid; u < rows * 2 * NFP; u += blockDim.x) {
-    const int m = u % NFP;
-    const int rest = u / NFP;
-    const int d = rest & 1;  // 0: x-face, 1: y-face
-    const int r = rest >> 1;
+  // ---- 3. per velocity row: L(f) = volume + lifted inflow jumps + collision ----
+  // A thread owns one (velocity, element) row: its NP nodal values live in
+  // registers; the derivative and lift tables are wave-uniform scalars.
+  for (int r = tid; r < rows; r += nthr) {
     const int q = r >> log2E, e = r & (E - 1);
     if (e >= Eb) continue;
     const int qg = q0 + q;
-    const int k = k0 + e;
-    const double c = d == 0 ? vex[qg] : vey[qg];
-    double J = 0.0;
-    if (c != 0.0) {
-      int face, own, nbnode;
-      if (d == 0) {
-        if (c > 0.0) { face = 3; own = N1 * m; nbnode = N1 * m + P; }
-        else         { face = 1; own = N1 * m + P; nbnode = N1 * m; }
-      } else {
-        if (c > 0.0) { face = 0; own = m; nbnode = m + N1 * P; }
-        else         { face = 2; own = m + N1 * P; nbnode = m; }
+    const bool first = r == r0;
+    double cx, cy, wq, gbx, gby, px[NFP], py[NFP];
+    int nbx, nby;
+    if (first) {
+      cx = cx0; cy = cy0; wq = wq0; gbx = gbx0; gby = gby0; nbx = nbx0; nby = nby0;
+#pragma unroll
+      for (int m = 0; m < NFP; ++m) {
+        px[m] = px0[m];
+        py[m] = py0[m];
       }
-      const int nb = neighbour(k, face, a);
-      const double fm = tile[r * S + own];
-      const double fp = nb >= 0 ? a.fs[(size_t)qg * KNP + (size_t)nb * NP + nbnode]
-                                : rw[(e * 4 + face) * NFP + m] * a.feqb[face * a.Q + qg];
-      J = (d == 0 ? a.fsx : a.fsy) * (-fabs(c)) * (fm - fp);  // e.n = -|c| on inflow
+    } else {
+      cx = vex[qg]; cy = vey[qg]; wq = vw[qg];
+      const int fx = cx > 0.0 ? 3 : 1, fy = cy > 0.0 ? 0 : 2;
+      nbx = nbr[e * 4 + fx];
+      nby = nbr[e * 4 + fy];
+      gbx = a.feqb[fx * a.Q + qg];
+      gby = a.feqb[fy * a.Q + qg];
+      const bool gx = cx != 0.0 && nbx >= 0, gy = cy != 0.0 && nby >= 0;
+      const double *sx = a.fs + (size_t)qg * KNP + (size_t)(nbx >= 0 ? nbx : 0) * NP + (cx > 0.0 ? P : 0);
+      const double *sy = a.fs + (size_t)qg * KNP + (size_t)(nby >= 0 ? nby : 0) * NP + (cy > 0.0 ? N1 * P : 0);
+#pragma unroll
+      for (int m = 0; m < NFP; ++m) {
+        px[m] = gx ? sx[N1 * m] : 0.0;
+        py[m] = gy ? sy[m] : 0.0;
+      }
     }
-    jump[r * 2 * NFP + d * NFP + m] = J;
+    // inflow faces of this velocity
+    const int fxc = cx > 0.0 ? 3 : 1, fyc = cy > 0.0 ? 0 : 2;
+    double f[NP];
+    double *row = tile + r * S;
+    if (Sh::VEC) {
+#pragma unroll
+      for (int c = 0; c < NP / 2; ++c) {
+        const double2v v = *reinterpret_cast<const double2v *>(row + 2 * c);
+        f[2 * c] = v[0];
+        f[2 * c + 1] = v[1];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NP; ++c) f[c] = row[c];
+    }
+    double kk[NP];
+    const double ax = cx * a.rx, ay = cy * a.sy;
+#pragma unroll
+    for (int j = 0; j < N1; ++j)
+#pragma unroll
+      for (int i = 0; i < N1; ++i) {
+        double dr = 0.0, ds = 0.0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+          dr += a.D1[i * N1 + m] * f[m + N1 * j];
+          ds += a.D1[j * N1 + m] * f[i + N1 * m];
+        }
+        kk[i + N1 * j] = -(ax * dr + ay * ds);
+      }
+    if (cx != 0.0) {
+      const double wx = a.fsx * (-fabs(cx));
+      const double *rwx = rw + (e * 4 + fxc) * NFP;
+#pragma unroll
+      for (int jj = 0; jj < N1; ++jj) {
+        const double own = cx > 0.0 ? f[N1 * jj] : f[N1 * jj + P];
+        const double ext = nbx >= 0 ? px[jj] : rwx[jj] * gbx;
+        const double J = wx * (own - ext);
+#pragma unroll
+        for (int ii = 0; ii < N1; ++ii) kk[ii + N1 * jj] += (cx > 0.0 ? a.lift_lo[ii] : a.lift_hi[ii]) * J;
+      }
+    }
+    if (cy != 0.0) {
+      const double wy = a.fsy * (-fabs(cy));
+      const double *rwy = rw + (e * 4 + fyc) * NFP;
+#pragma unroll
+      for (int ii = 0; ii < N1; ++ii) {
+        const double own = cy > 0.0 ? f[ii] : f[ii + N1 * P];
+        const double ext = nby >= 0 ? py[ii] : rwy[ii] * gby;
+        const double J = wy * (own - ext);
+#pragma unroll
+        for (int jj = 0; jj < N1; ++jj) kk[ii + N1 * jj] += (cy > 0.0 ? a.lift_lo[jj] : a.lift_hi[jj]) * J;
+      }
+    }
+    const double *mm = mom + e * NP * 4;
+#pragma unroll
+    for (int nn = 0; nn < NP; ++nn) {
+      const double4v m4 = *reinterpret_cast<const double4v *>(mm + 4 * nn);
+      const double eu = cx * m4[0] + cy * m4[1];
+      const double feq = wq * m4[2] * (m4[3] + eu * (a.theta_inv + eu * a.half_theta2_inv));
+      kk[nn] += (feq - f[nn]) * a.inv_tau;
+    }
+    if (Sh::VEC) {
+#pragma unroll
+      for (int c = 0; c < NP / 2; ++c)
+        *reinterpret_cast<double2v *>(row + 2 * c) = double2v{kk[2 * c], kk[2 * c + 1]};
+    } else {
+#pragma unroll
+      for (int c = 0; c < NP; ++c) row[c] = kk[c];
+    }
   }
   __syncthreads();
 
-  // ---- 4. volume + surface + collision + RK4 update ----------------------------
-  if (!active) return;
-  const int i = n % N1, j = n / N1;
-  double dri[N1], dsj[N1];
+  // ---- 4. RK4 register update, coalesced over each velocity row -----------------
+  const double cacc = a.c_acc, cout = a.c_out;
+  // x: f_s (stage 1), f_n (stages 2, 3), acc (stage 4); y: acc (stages 2, 3)
+  const double *xr = (MODE == 1 ? a.fs : MODE == 2 ? a.fn : a.acc) + boff;
+  double *accr = a.acc + boff;
+  double *outr = a.out + boff;
+  for (int c0 = tid; c0 < nch; c0 += nthr * U) {
+    V kv[U], x[U], y[U];
+    size_t go[U];
+    bool ok[U];
+    const bool all = full && c0 - tid + U * nthr <= nch;
 #pragma unroll
-  for (int m = 0; m < N1; ++m) {
-    dri[m] = a.D1[i * N1 + m];
-    dsj[m] = a.D1[j * N1 + m];
-  }
-  const double llo_i = a.lift_lo[i], lhi_i = a.lift_hi[i];
-  const double llo_j = a.lift_lo[j], lhi_j = a.lift_hi[j];
-  for (int r = g; r < rows; r += G) {
-    const int q = r >> log2E, e = r & (E - 1);
-    if (e >= Eb) continue;
-    const int qg = q0 + q;
-    const double cx = vex[qg], cy = vey[qg], wq = vw[qg];
-    const double *row = tile + r * S;
-    double dr = 0.0, ds = 0.0;
-#pragma unroll
-    for (int m = 0; m < N1; ++m) {
-      dr += dri[m] * row[m + N1 * j];
-      ds += dsj[m] * row[i + N1 * m];
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * nthr;
+      int q, e, w;
+      split_access<CPE>(c, cpr, log2E, q, e, w);
+      ok[u] = all || (c < nch && e < Eb);
+      go[u] = (size_t)q * KNP + CW * w;
+      if (ok[u]) kv[u] = lds_get<V>(tile + (q * E + e) * S + CW * (w - e * CPE));
     }
-    const double fq = row[n];
-    const double vol = -(cx * a.rx * dr + cy * a.sy * ds);
-    const double *jr = jump + r * 2 * NFP;
-    const double surf = (cx > 0.0 ? llo_i : lhi_i) * jr[j] + (cy > 0.0 ? llo_j : lhi_j) * jr[NFP + i];
-    const double *mm = mom + (e * NP + n) * 4;
-    const double eu = cx * mm[0] + cy * mm[1];
-    const double feq = wq * mm[2] * (mm[3] + eu * (a.theta_inv + eu * a.half_theta2_inv));
-    const double coll = (feq - fq) * a.inv_tau;
-    const double kv = vol + surf + coll;
-    const size_t gi = (size_t)qg * KNP + (size_t)(k0 + e) * NP + n;
-    switch (a.stage) {
-      case 0:
-        a.out[gi] = kv;
-        break;
-      case 1:
-        a.acc[gi] = fq + a.c_acc * kv;
-        a.out[gi] = fq + a.c_out * kv;
-        break;
-      case 2:
-      case 3: {
-        const double ac = a.acc[gi];
-        const double f0 = a.fn[gi];
-        a.acc[gi] = ac + a.c_acc * kv;
-        a.out[gi] = f0 + a.c_out * kv;
-        break;
-      }
-      default:
-        a.out[gi] = a.acc[gi] + a.c_acc * kv;
-        break;
+    if (MODE != 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ok[u]) x[u] = *reinterpret_cast<const V *>(xr + go[u]);
+    }
+    if (MODE == 2) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ok[u]) y[u] = *reinterpret_cast<const V *>(accr + go[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!ok[u]) continue;
+      V o, an;
+      rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
+      *reinterpret_cast<V *>(outr + go[u]) = o;
+      if (MODE == 1 || MODE == 2) *reinterpret_cast<V *>(accr + go[u]) = an;
     }
   }
 }
@@ -368,25 +548,38 @@ __global__ void u64_to_f64_kernel(const unsigned long long *src, double *dst) {
   if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = __longlong_as_double((long long)src[0]);
 }
 
-template <int P>
-hipError_t launch_stage_p(const StageArgs &a, size_t lds, int ntiles, hipStream_t st) {
+template <int P, int MODE>
+hipError_t launch_stage_pm(const StageArgs &a, size_t lds, int ntiles, hipStream_t st) {
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)stage_kernel<P>,
+    hipError_t e = hipFuncSetAttribute((const void *)stage_kernel<P, MODE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   dim3 grid((unsigned)a.nblk, (unsigned)ntiles);
-  hipLaunchKernelGGL(stage_kernel<P>, grid, dim3(kBlock), lds, st, a);
+  hipLaunchKernelGGL((stage_kernel<P, MODE>), grid, dim3(kBlock), lds, st, a);
   return hipGetLastError();
+}
+
+
+
+template <int P>
+hipError_t launch_stage_p(const StageArgs &a, size_t lds, int ntiles, hipStream_t st) {
+  switch (a.stage) {
+    case 0: return launch_stage_pm<P, 0>(a, lds, ntiles, st);
+    case 1: return launch_stage_pm<P, 1>(a, lds, ntiles, st);
+    case 2:
+    case 3: return launch_stage_pm<P, 2>(a, lds, ntiles, st);
+    case 4: return launch_stage_pm<P, 4>(a, lds, ntiles, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
 size_t stage_lds_bytes(int p, int E, int Qt) {
   const int N1 = p + 1, NP = N1 * N1;
-  const int S = (NP % 2 == 0) ? NP + 1 : NP;
-  const int G = kBlock / NP, T = G * NP;
-  return (size_t)lds_layout(NP, N1, S, T, E, Qt).total * sizeof(double);
+  const int S = (NP % 2 == 0) ? NP + 2 : NP;
+  return (size_t)lds_layout(NP, N1, S, E, Qt).total * sizeof(double);
 }
 
 hipError_t launch_stage(int p, const StageArgs &a, size_t lds, int ntiles, hipStream_t st) {

@@ -22,6 +22,7 @@ struct StageArgs {
   const double *feqb;  // [4][Q]: f^eq_q(1, u_b) of each side's wall velocity
   const double *mom;   // [3][K*Np]: rho, ux, uy  (tiled mode only)
   const double *rhow;  // [K][4][Nfp]: diffuse-wall densities (tiled mode only)
+  const double *wmom;  // [Q][16]: moment weights 1, e_x, e_y, outgoing |e.n| per side, 0...
   double *rhow_out;    // optional [K][4][Nfp] copy of the wall densities (fused mode)
   double D1[kMaxN1 * kMaxN1];  // 1-D GLL differentiation matrix
   double lift_lo[kMaxN1];      // M1^{-1} e_0: lift of a flux on the left / bottom face
