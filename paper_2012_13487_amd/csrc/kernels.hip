@@ -113,6 +113,28 @@ __device__ __forceinline__ void split_access(int c, int cpr, int log2E, int &q, 
   e = w / CPE;
 }
 
+// Exterior traces of the two inflow faces of one velocity row: a column of the
+// x-neighbour (stride N1) and a contiguous row of the y-neighbour (two nodes
+// per 16-byte access when N1 is even: that row then starts 16-byte aligned).
+template <int N1, int NFP>
+__device__ __forceinline__ void load_face_traces(const double *sx, const double *sy, bool gx, bool gy,
+                                                 double (&px)[NFP], double (&py)[NFP]) {
+#pragma unroll
+  for (int m = 0; m < NFP; ++m) px[m] = gx ? sx[N1 * m] : 0.0;
+  if (N1 % 2 == 0) {
+#pragma unroll
+    for (int m = 0; m < NFP; m += 2) {
+      double2v v = {0.0, 0.0};
+      if (gy) v = *reinterpret_cast<const double2v *>(sy + m);
+      py[m] = v[0];
+      py[m + 1] = v[1];
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < NFP; ++m) py[m] = gy ? sy[m] : 0.0;
+  }
+}
+
 __device__ inline int neighbour(int k, int face, const StageArgs &a) {
   const int ex = k % a.nx, ey = k / a.nx;
   switch (face) {
@@ -158,34 +180,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
   const double *vey = a.vel + a.Q;
   const double *vw = a.vel + 2 * a.Q;
 
-  // ---- 0. loads of this thread's first velocity row that do not depend on the
-  //         stage's arithmetic (velocity, weights, exterior traces): issued
-  //         first so that they are in flight during phases 1 and 2
-  const int r0 = tid;
-  double cx0 = 0.0, cy0 = 0.0, wq0 = 0.0, gbx0 = 0.0, gby0 = 0.0;
-  double px0[NFP], py0[NFP];
-  int nbx0 = -1, nby0 = -1;
-  if (r0 < rows && (r0 & (E - 1)) < Eb) {
-    const int q = r0 >> log2E, e = r0 & (E - 1), qg = q0 + q;
-    cx0 = vex[qg];
-    cy0 = vey[qg];
-    wq0 = vw[qg];
-    const int fxc = cx0 > 0.0 ? 3 : 1, fyc = cy0 > 0.0 ? 0 : 2;
-    nbx0 = neighbour(k0 + e, fxc, a);
-    nby0 = neighbour(k0 + e, fyc, a);
-    gbx0 = a.feqb[fxc * a.Q + qg];
-    gby0 = a.feqb[fyc * a.Q + qg];
-    const double *sx = a.fs + (size_t)qg * KNP + (size_t)(nbx0 >= 0 ? nbx0 : 0) * NP + (cx0 > 0.0 ? P : 0);
-    const double *sy = a.fs + (size_t)qg * KNP + (size_t)(nby0 >= 0 ? nby0 : 0) * NP + (cy0 > 0.0 ? N1 * P : 0);
-    const bool gx = cx0 != 0.0 && nbx0 >= 0, gy = cy0 != 0.0 && nby0 >= 0;
-#pragma unroll
-    for (int m = 0; m < NFP; ++m) {
-      px0[m] = gx ? sx[N1 * m] : 0.0;
-      py0[m] = gy ? sy[m] : 0.0;
-    }
-  }
-
-  // ---- 0b. neighbours of the block's elements (-1: wall) -----------------------
+  // ---- 0. neighbours of the block's elements (-1: wall) -----------------------
   if (tid < E * 4) {
     const int e = tid >> 2, fc = tid & 3;
     nbr[tid] = e < Eb ? neighbour(k0 + e, fc, a) : -1;
@@ -232,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
       const int e = t / NB, nb = t % NB;
       const int node = nb * 16 + (lane & 15);
       const int qa = sl * qper, qe = min(Qb, qa + qper);
-      double4v acc = {0.0, 0.0, 0.0, 0.0};
+      double4v acc = {0.0, 0.0, 0.0, 0.0}, acc1 = acc, acc2 = acc, acc3 = acc;
       if (e < Eb) {
         constexpr int KB = 16;  // 4-velocity steps whose operands are loaded together
         for (int qb = qa; qb < qe; qb += 4 * KB) {
@@ -245,9 +240,15 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
             bv[t] = (in && node < NP) ? tile[(q * E + e) * S + node] : 0.0;
           }
 #pragma unroll
-          for (int t = 0; t < KB; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc, 0, 0, 0);
+          for (int t = 0; t < KB; t += 4) {  // four independent accumulation chains
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t + 1], bv[t + 1], acc1, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t + 2], bv[t + 2], acc2, 0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t + 3], bv[t + 3], acc3, 0, 0, 0);
+          }
         }
       }
+      acc += acc1 + acc2 + acc3;
       // register v of a lane holds C[4 v + lane / 16][lane % 16]; rows 0..6 are used
       if (node < NP) {
         double *pp = part + ((size_t)pr * 7) * 16;
@@ -319,31 +320,16 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
     const int q = r >> log2E, e = r & (E - 1);
     if (e >= Eb) continue;
     const int qg = q0 + q;
-    const bool first = r == r0;
-    double cx, cy, wq, gbx, gby, px[NFP], py[NFP];
-    int nbx, nby;
-    if (first) {
-      cx = cx0; cy = cy0; wq = wq0; gbx = gbx0; gby = gby0; nbx = nbx0; nby = nby0;
-#pragma unroll
-      for (int m = 0; m < NFP; ++m) {
-        px[m] = px0[m];
-        py[m] = py0[m];
-      }
-    } else {
-      cx = vex[qg]; cy = vey[qg]; wq = vw[qg];
-      const int fx = cx > 0.0 ? 3 : 1, fy = cy > 0.0 ? 0 : 2;
-      nbx = nbr[e * 4 + fx];
-      nby = nbr[e * 4 + fy];
-      gbx = a.feqb[fx * a.Q + qg];
-      gby = a.feqb[fy * a.Q + qg];
+    const double cx = vex[qg], cy = vey[qg], wq = vw[qg];
+    // exterior traces of the two inflow faces (their loads overlap the volume term)
+    const int nbx = nbr[e * 4 + (cx > 0.0 ? 3 : 1)], nby = nbr[e * 4 + (cy > 0.0 ? 0 : 2)];
+    const double gbx = a.feqb[(cx > 0.0 ? 3 : 1) * a.Q + qg], gby = a.feqb[(cy > 0.0 ? 0 : 2) * a.Q + qg];
+    double px[NFP], py[NFP];
+    {
       const bool gx = cx != 0.0 && nbx >= 0, gy = cy != 0.0 && nby >= 0;
       const double *sx = a.fs + (size_t)qg * KNP + (size_t)(nbx >= 0 ? nbx : 0) * NP + (cx > 0.0 ? P : 0);
       const double *sy = a.fs + (size_t)qg * KNP + (size_t)(nby >= 0 ? nby : 0) * NP + (cy > 0.0 ? N1 * P : 0);
-#pragma unroll
-      for (int m = 0; m < NFP; ++m) {
-        px[m] = gx ? sx[N1 * m] : 0.0;
-        py[m] = gy ? sy[m] : 0.0;
-      }
+      load_face_traces<N1, NFP>(sx, sy, gx, gy, px, py);
     }
     // inflow faces of this velocity
     const int fxc = cx > 0.0 ? 3 : 1, fyc = cy > 0.0 ? 0 : 2;
