@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--resid-every", type=int, default=50)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 1 GiB (5 times), to scale the "
+                         "FETCH_SIZE / WRITE_SIZE counters of the stage kernel")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -90,6 +93,15 @@ def main():
     from paper_2012_13487_amd import Solver
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read": x.numel() * 8,
+                          "bytes_written": x.numel() * 8, "launches": 5}), flush=True)
+        return
     spec = workloads.CAVITY_64x64_P3_NC16
     g = Solver.from_spec(spec, stream="torch", torch_memory=True)
     dt = g.stable_dt(spec.cfl)
