@@ -15,8 +15,11 @@
  *   - uniform Cartesian quadrilaterals, element k = ex + nx*ey, ex in [0,nx),
  *     ey in [0,ny); (p+1)^2 Gauss-Lobatto-Legendre nodes per element, node
  *     n = i + (p+1)*j, i along x, j along y;
- *   - distribution function stored as f[q][k][n] (velocity-major SoA), FP64 on
- *     the host side of every call;
+ *   - host arrays of the distribution function (set_state, get_state, rhs,
+ *     wall_density) are f[q][k][n], velocity-major, FP64; on the device the
+ *     library keeps f element-major, f[k][q][n] (the Q velocity rows of an
+ *     element, each Np contiguous nodes, are consecutive), so that the tile of
+ *     one element streams as a single contiguous block;
  *   - sides / faces: 0 bottom (y = y0), 1 right (x = x0+lx), 2 top
  *     (y = y0+ly), 3 left (x = x0); face nodes ordered by increasing i or j;
  *   - 2-D tensor velocity sets: q = a + m*b with e_q = (x_a, x_b).
@@ -154,8 +157,8 @@ int dgbgk_init_equilibrium(dgbgk_solver *s, double rho0, double ux0, double uy0)
 int dgbgk_set_state(dgbgk_solver *s, const double *f, size_t count);
 int dgbgk_get_state(dgbgk_solver *s, double *f, size_t count);
 
-/* Device address of the current state f[q][k][n] (FP64, Q*K*Np doubles),
- * valid until the next dgbgk_step(); for zero-copy views. */
+/* Device address of the current state, element-major f[k][q][n] (FP64,
+ * Q*K*Np doubles), valid until the next dgbgk_step(); for zero-copy views. */
 int dgbgk_state_device_ptr(dgbgk_solver *s, void **ptr);
 
 /* Advance nsteps classical RK4 steps of size dt (enqueued; returns at once).
@@ -194,10 +197,16 @@ int dgbgk_synchronize(dgbgk_solver *s);
 
 /* Work decomposition of the stage kernel.  mode 0: automatic (all
  * velocities of a block of elements per work-group when the tile fits in LDS,
- * else velocity tiles); 1: force the all-velocity (fused) form; 2: force
- * velocity tiles of velocities_per_tile (0 = largest that fits).  The tiled
- * form reduces the node moments in a separate pass.  Results agree to
- * rounding; this exists for testing and tuning. */
+ * else velocity tiles); 1 and 3: force the all-velocity (fused) form with one
+ * work-group per element block; 2: force velocity tiles of
+ * velocities_per_tile (0 = largest that fits); 4: the fused form run by
+ * persistent wave-specialised work-groups that each walk a run of blocks
+ * (p <= 3, at most 256 velocity rows per block; DGBGK_EINVAL otherwise).  The
+ * tiled form reduces the node moments in a separate pass.  get_tiling reports
+ * *fused = 0 (velocity tiles), 1 (fused, one work-group per block) or 2
+ * (fused, persistent), and the LDS bytes per work-group.  The fused forms
+ * give bit-identical results; the tiled form agrees to rounding.  This exists
+ * for testing and tuning. */
 int dgbgk_set_tiling(dgbgk_solver *s, int32_t mode, int32_t velocities_per_tile);
 int dgbgk_get_tiling(const dgbgk_solver *s, int32_t *fused, int32_t *elems_per_group,
                      int32_t *velocities_per_tile, size_t *lds_bytes);

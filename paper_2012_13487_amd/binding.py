@@ -251,8 +251,9 @@ class Solver:
     def tiling(self):
         fused, e, qt, lds = C.c_int32(), C.c_int32(), C.c_int32(), C.c_size_t()
         self._call("dgbgk_get_tiling", C.byref(fused), C.byref(e), C.byref(qt), C.byref(lds))
-        return {"fused": bool(fused.value), "elems_per_group": e.value,
-                "velocities_per_tile": qt.value, "lds_bytes": lds.value}
+        return {"fused": bool(fused.value), "persistent": fused.value == 2,
+                "elems_per_group": e.value, "velocities_per_tile": qt.value,
+                "lds_bytes": lds.value}
 
     # -- device work
     def init_equilibrium(self, rho0=1.0, ux0=0.0, uy0=0.0):

@@ -5,6 +5,7 @@
 // time step runs in the kernels of kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -22,6 +23,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kFusedLdsLimit = 64 * 1024;  // keeps >= 2 work-groups per CU
+constexpr size_t kStreamLdsLimit = 160 * 1024;  // one persistent work-group per CU
 constexpr int kMaxQ = 4096;
 
 size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -75,6 +77,8 @@ struct dgbgk_solver {
   unsigned long long *d_u64 = nullptr;
   // launch configuration
   int fused = 1, E = 1, log2E = 0, Qt = 0, ntiles = 1, nblk = 1;
+  int persistent = 0;  // fused blocks run by the persistent pipelined kernel
+  int num_cu = 256;
   size_t lds = 0;
   int tiling_mode = 0, tiling_qt = 0;
   // state
@@ -142,10 +146,14 @@ void choose_tiling(dgbgk_solver *s) {
   const int NP = s->Np;
   const int G = kBlock / NP;
   int E = 1;
-  while (E * 2 <= G && (int64_t)E * 2 * s->Q * NP <= 4096 && E * 2 <= s->K) E *= 2;
+  // for orders the persistent kernel serves, keep one velocity row per thread
+  const bool row_cap = s->p <= kStreamMaxP;
+  while (E * 2 <= G && (int64_t)E * 2 * s->Q * NP <= 4096 && E * 2 <= s->K &&
+         (!row_cap || (int64_t)E * 2 * s->Q <= kBlock))
+    E *= 2;
   size_t lds = stage_lds_bytes(s->p, E, s->Q);
   bool fused = lds <= kFusedLdsLimit;
-  if (s->tiling_mode == 1) fused = true;
+  if (s->tiling_mode == 1 || s->tiling_mode == 3 || s->tiling_mode == 4) fused = true;
   if (s->tiling_mode == 2) fused = false;
   if (fused) {
     s->fused = 1;
@@ -166,6 +174,9 @@ void choose_tiling(dgbgk_solver *s) {
   s->log2E = 0;
   while ((1 << s->log2E) < E) ++s->log2E;
   s->nblk = (int)((s->K + E - 1) / E);
+  s->persistent = s->fused && s->tiling_mode == 4 && stream_applicable(s->p, E, s->Q, s->K) &&
+                  stream_lds_bytes(s->p, E, s->Q) <= kStreamLdsLimit;
+  if (s->persistent) lds = stream_lds_bytes(s->p, E, s->Q);
   s->lds = lds;
 }
 
@@ -180,6 +191,7 @@ int ensure_device(dgbgk_solver *s) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(s, DGBGK_EDEVICE, "device %d is %s; this library is built for gfx950", dev,
                 prop.gcnArchName);
+  if (prop.multiProcessorCount > 0) s->num_cu = prop.multiProcessorCount;
   if (s->lds > prop.sharedMemPerBlock && s->lds > 65536)
     return fail(s, DGBGK_EDEVICE, "stage kernel needs %zu B of LDS, device allows %zu", s->lds,
                 (size_t)prop.sharedMemPerBlock);
@@ -299,7 +311,12 @@ int run_stage(dgbgk_solver *s, int stage, const double *fs, double *out, double 
     case 4: a.c_acc = dt / 6.0; a.c_out = 0.0; break;
     default: break;
   }
-  e = launch_stage(s->p, a, s->lds, s->ntiles, s->stream);
+  if (s->persistent) {
+    const int groups = (int)std::min<int64_t>(s->nblk, (int64_t)s->num_cu);
+    e = launch_stream(s->p, a, s->lds, groups, s->stream);
+  } else {
+    e = launch_stage(s->p, a, s->lds, s->ntiles, s->stream);
+  }
   if (e != hipSuccess) return hip_fail(s, e, "stage kernel");
   return DGBGK_OK;
 }
@@ -561,7 +578,9 @@ int dgbgk_set_state(dgbgk_solver *s, const double *f, size_t count) {
   if (!f || count != need) return fail(s, DGBGK_EINVAL, "state needs %zu doubles", need);
   int rc = ensure_device(s);
   if (rc) return rc;
-  hipError_t e = hipMemcpyAsync(s->d_fn, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  // host order f[q][k][n] into a stage buffer, then element-major into f_n
+  hipError_t e = hipMemcpyAsync(s->d_b, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = launch_transpose(s->d_b, s->d_fn, (int)s->K, s->Np, s->Q, 1, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "set_state copy");
   s->have_state = true;
@@ -574,7 +593,9 @@ int dgbgk_get_state(dgbgk_solver *s, double *f, size_t count) {
   const size_t need = (size_t)s->K * s->Np * s->Q;
   if (!f || count != need) return fail(s, DGBGK_EINVAL, "state needs %zu doubles", need);
   if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
-  hipError_t e = hipMemcpyAsync(f, s->d_fn, need * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  hipError_t e = launch_transpose(s->d_fn, s->d_b, (int)s->K, s->Np, s->Q, 0, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(f, s->d_b, need * sizeof(double), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "get_state copy");
   return DGBGK_OK;
@@ -613,10 +634,13 @@ int dgbgk_rhs(dgbgk_solver *s, const double *f, double *k, size_t count) {
   if (!f || !k || count != need) return fail(s, DGBGK_EINVAL, "arrays need %zu doubles", need);
   int rc = ensure_device(s);
   if (rc) return rc;
-  hipError_t e = hipMemcpyAsync(s->d_a, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  hipError_t e = hipMemcpyAsync(s->d_b, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = launch_transpose(s->d_b, s->d_a, (int)s->K, s->Np, s->Q, 1, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "rhs input copy");
   if ((rc = run_stage(s, 0, s->d_a, s->d_b, 0.0))) return rc;
-  e = hipMemcpyAsync(k, s->d_b, need * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  e = launch_transpose(s->d_b, s->d_a, (int)s->K, s->Np, s->Q, 0, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(k, s->d_a, need * sizeof(double), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "rhs output copy");
   return DGBGK_OK;
@@ -629,7 +653,8 @@ int dgbgk_wall_density(dgbgk_solver *s, const double *f, double *out, size_t cou
   if (!f || !out || count != need) return fail(s, DGBGK_EINVAL, "state needs %zu doubles", need);
   int rc = ensure_device(s);
   if (rc) return rc;
-  hipError_t e = hipMemcpyAsync(s->d_a, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  hipError_t e = hipMemcpyAsync(s->d_b, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = launch_transpose(s->d_b, s->d_a, (int)s->K, s->Np, s->Q, 1, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "wall_density input copy");
   e = launch_fill_u64((unsigned long long *)s->d_rhow, nout, 0ull, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "fill kernel");
@@ -718,12 +743,18 @@ int dgbgk_steps_taken(const dgbgk_solver *s, int64_t *steps) {
 
 int dgbgk_set_tiling(dgbgk_solver *s, int32_t mode, int32_t velocities_per_tile) {
   if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
-  if (mode < 0 || mode > 2) return fail(s, DGBGK_EINVAL, "mode must be 0, 1 or 2");
+  if (mode < 0 || mode > 4) return fail(s, DGBGK_EINVAL, "mode must be 0..4");
   if (velocities_per_tile < 0) return fail(s, DGBGK_EINVAL, "velocities_per_tile must be >= 0");
   const int saved_mode = s->tiling_mode, saved_qt = s->tiling_qt;
   s->tiling_mode = mode;
   s->tiling_qt = velocities_per_tile;
   choose_tiling(s);
+  if (mode == 4 && !s->persistent) {
+    s->tiling_mode = saved_mode;
+    s->tiling_qt = saved_qt;
+    choose_tiling(s);
+    return fail(s, DGBGK_EINVAL, "the persistent kernel does not apply to this problem");
+  }
   if (s->fused && s->lds > 160 * 1024) {
     s->tiling_mode = saved_mode;
     s->tiling_qt = saved_qt;
@@ -736,7 +767,7 @@ int dgbgk_set_tiling(dgbgk_solver *s, int32_t mode, int32_t velocities_per_tile)
 int dgbgk_get_tiling(const dgbgk_solver *s, int32_t *fused, int32_t *elems_per_group,
                      int32_t *velocities_per_tile, size_t *lds_bytes) {
   if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
-  if (fused) *fused = s->fused;
+  if (fused) *fused = s->fused ? (s->persistent ? 2 : 1) : 0;
   if (elems_per_group) *elems_per_group = s->E;
   if (velocities_per_tile) *velocities_per_tile = s->Qt;
   if (lds_bytes) *lds_bytes = s->lds;

@@ -21,6 +21,7 @@
 // than being padded out to matrix-core tiles.
 #include "kernels.hpp"
 
+#include <cstdint>
 #include <cmath>
 #include <type_traits>
 
@@ -104,13 +105,26 @@ __device__ __forceinline__ double lds_get<double>(const double *p) { return *p; 
 template <>
 __device__ __forceinline__ double2v lds_get<double2v>(const double *p) { return *reinterpret_cast<const double2v *>(p); }
 
-// Access c of a block's f tile (CW doubles each, CPE per element and velocity):
-// velocity q, element e, access w within the velocity row.
+// n / d for 0 <= n < 2^22, d >= 1: a reciprocal estimate, then one exact
+// correction step.
+__device__ __forceinline__ int div_small(int n, int d) {
+  int t = (int)(((float)n + 0.5f) * __builtin_amdgcn_rcpf((float)d));
+  if (t * d > n) --t;
+  if ((t + 1) * d <= n) ++t;
+  return t;
+}
+
+// f is stored element-major, f[k][q][n]: the Q velocity rows of an element are
+// consecutive, each NP contiguous nodes.  A block tile (E elements, Qb
+// velocities from q0) is read in memory order: access c (CW doubles; CPE per
+// velocity row) is element e, velocity q, access w within the row, at offset
+// e * Q * NP + q * NP + CW * w from the tile origin.
 template <int CPE>
-__device__ __forceinline__ void split_access(int c, int cpr, int log2E, int &q, int &e, int &w) {
-  q = (c >> log2E) / CPE;
-  w = c - q * cpr;
-  e = w / CPE;
+__device__ __forceinline__ void split_access(int c, int Qb, int E, int &q, int &e, int &w) {
+  const int cq = c / CPE;
+  w = c - cq * CPE;
+  e = E == 1 ? 0 : div_small(cq, Qb);
+  q = cq - e * Qb;
 }
 
 // Exterior traces of the two inflow faces of one velocity row: a column of the
@@ -145,15 +159,301 @@ __device__ inline int neighbour(int k, int face, const StageArgs &a) {
   }
 }
 
+// Global accesses at a wave-uniform base plus a 32-bit per-lane offset (in
+// doubles; the caller guarantees offset * 8 < 2^32), so that each access
+// needs one offset register rather than a 64-bit address.
+template <typename V>
+__device__ __forceinline__ V ld32(const double *base, uint32_t off) {
+  return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(base) + (off << 3));
+}
+template <typename V>
+__device__ __forceinline__ void st32(double *base, uint32_t off, const V &v) {
+  *reinterpret_cast<V *>(reinterpret_cast<char *>(base) + (off << 3)) = v;
+}
+
+// Coalesced copy of a block's f tile (E elements x Qb velocities) between HBM
+// and registers: access u of a thread is c = tid + u * nthr.
+template <int CPE, int CW, int NP, int PF, typename V>
+__device__ __forceinline__ void load_tile(V (&pf)[PF], const double *src, int tid, int nthr, int nch,
+                                          int Qb, int E, int Eb, uint32_t QNP) {
+#pragma unroll
+  for (int u = 0; u < PF; ++u) {
+    const int c = tid + u * nthr;
+    int q, e, w;
+    split_access<CPE>(c, Qb, E, q, e, w);
+    if (c < nch && e < Eb) pf[u] = ld32<V>(src, (uint32_t)e * QNP + (uint32_t)(q * NP + CW * w));
+  }
+}
+
+// Node moments and diffuse-wall densities of a block whose f tile is in LDS.
+// C[c][n] = sum_q W[q][c] f[q][n] with W[q] = (1, e_x, e_y, outgoing normal
+// speed at the bottom, right, top, left wall): a dense (7 x Q) x (Q x NP)
+// product per element, on FP64 matrix cores (16x16x4 steps; K split over the
+// wavefronts, partial products summed through LDS).  wsrc points at the
+// weights of the block's first velocity ([q][16]).  Threads 0..nthr-1 take
+// part; this writes the partial products, and block_moments_combine (after a
+// barrier) sums them.  KB 4-velocity steps have their operands loaded
+// together.
+__host__ __device__ inline int moment_slices(int P, int E) {
+  const int tasks = E * (((P + 1) * (P + 1) + 15) / 16);
+  return tasks >= 4 ? 1 : 4 / tasks;
+}
+
+// Moment weight c of a velocity (the columns of W above): 1, e_x, e_y, then
+// the outgoing normal speed at the bottom, right, top and left wall.
+__device__ __forceinline__ double moment_weight(int c, double cx, double cy) {
+  switch (c) {
+    case 0: return 1.0;
+    case 1: return cx;
+    case 2: return cy;
+    case 3: return cy < 0.0 ? -cy : 0.0;
+    case 4: return cx > 0.0 ? cx : 0.0;
+    case 5: return cy > 0.0 ? cy : 0.0;
+    case 6: return cx < 0.0 ? -cx : 0.0;
+    default: return 0.0;
+  }
+}
+
+// WV: wsrc holds the velocities (e_x[Qb] then e_y[Qb]) and the weights are
+// formed in registers; otherwise wsrc is the [q][16] weight table.
+template <int P, int KB, bool WV = false>
+__device__ __forceinline__ void block_moments_mfma(const double *tile, double *part, const double *wsrc,
+                                                   int E, int Qb, int Eb, int tid, int nthr) {
+  using Sh = Shape<P>;
+  constexpr int NP = Sh::NP, S = Sh::S;
+  constexpr int NB = (NP + 15) / 16;  // 16-node column blocks of the moment product
+  const int wave = tid >> 6, lane = tid & 63;
+  const int tasks = E * NB;                     // (element, 16-node block)
+  const int ks = moment_slices(P, E);           // K slices per task
+  const int qper = ((Qb + ks - 1) / ks + 3) / 4 * 4;
+  for (int pr = wave; pr < tasks * ks; pr += nthr >> 6) {
+    const int t = pr / ks, sl = pr % ks;
+    const int e = t / NB, nb = t % NB;
+    const int node = nb * 16 + (lane & 15);
+    const int qa = sl * qper, qe = min(Qb, qa + qper);
+    double4v acc = {0.0, 0.0, 0.0, 0.0}, acc1 = acc, acc2 = acc, acc3 = acc;
+    if (e < Eb) {
+#pragma unroll 1
+      for (int qb = qa; qb < qe; qb += 4 * KB) {
+        double av[KB], bv[KB];
+#pragma unroll
+        for (int t2 = 0; t2 < KB; ++t2) {
+          const int q = qb + 4 * t2 + (lane >> 4);
+          const bool in = q < qe;
+          if (WV) av[t2] = in ? moment_weight(lane & 15, wsrc[q], wsrc[Qb + q]) : 0.0;
+          else av[t2] = in ? wsrc[(size_t)q * 16 + (lane & 15)] : 0.0;
+          bv[t2] = (in && node < NP) ? tile[(q * E + e) * S + node] : 0.0;
+        }
+#pragma unroll
+        for (int t2 = 0; t2 < KB; t2 += 4) {  // four independent accumulation chains
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t2], bv[t2], acc, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t2 + 1], bv[t2 + 1], acc1, 0, 0, 0);
+          acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t2 + 2], bv[t2 + 2], acc2, 0, 0, 0);
+          acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t2 + 3], bv[t2 + 3], acc3, 0, 0, 0);
+        }
+      }
+    }
+    acc += acc1 + acc2 + acc3;
+    // register v of a lane holds C[4 v + lane / 16][lane % 16]; rows 0..6 are used
+    if (node < NP) {
+      double *pp = part + ((size_t)pr * 7) * 16;
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int row = 4 * v + (lane >> 4);
+        if (row < 7) pp[row * 16 + (lane & 15)] = acc[v];
+      }
+    }
+  }
+}
+
+// Sums the partial products into mom (ux, uy, rho, 1 - |u|^2 / (2 theta) per
+// node) and the wall densities rw ([e][face][NFP]); the caller synchronises
+// afterwards.
+template <int P>
+__device__ __forceinline__ void block_moments_combine(const StageArgs &a, const double *part,
+                                                      double *mom, double *rw, const int *nbr,
+                                                      int E, int Eb, int k0, int tid) {
+  using Sh = Shape<P>;
+  constexpr int N1 = Sh::N1, NP = Sh::NP, NFP = Sh::NFP;
+  constexpr int NB = (NP + 15) / 16;
+  const int ks = moment_slices(P, E);
+  if (tid < E * NP) {
+    const int e2 = tid / NP, n2 = tid % NP;
+    if (e2 < Eb) {
+      const int t = e2 * NB + n2 / 16, col = n2 % 16;
+      double sm[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int sl = 0; sl < ks; ++sl) {
+        const double *pp = part + ((size_t)(t * ks + sl) * 7) * 16;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) sm[c] += pp[c * 16 + col];
+      }
+      const double rho = sm[0], ux = sm[1] / rho, uy = sm[2] / rho;
+      double *m = mom + (e2 * NP + n2) * 4;
+      m[0] = ux;
+      m[1] = uy;
+      m[2] = rho;
+      m[3] = 1.0 - (ux * ux + uy * uy) * a.half_theta_inv;
+      if (a.wall_mask != 0) {
+        const int i2 = n2 % N1, j2 = n2 / N1;
+        const bool on[4] = {nbr[e2 * 4 + 0] < 0 && j2 == 0, nbr[e2 * 4 + 1] < 0 && i2 == P,
+                            nbr[e2 * 4 + 2] < 0 && j2 == P, nbr[e2 * 4 + 3] < 0 && i2 == 0};
+        const int fm[4] = {i2, j2, i2, j2};
+#pragma unroll
+        for (int fc = 0; fc < 4; ++fc)
+          if (on[fc]) {
+            const double v = sm[3 + fc] * a.wall_den_inv[fc];
+            rw[(e2 * 4 + fc) * NFP + fm[fc]] = v;
+            if (a.rhow_out) a.rhow_out[((size_t)(k0 + e2) * 4 + fc) * NFP + fm[fc]] = v;
+          }
+      }
+    }
+  }
+}
+
+// Exterior traces of the two inflow faces of velocity qg at element k (zero
+// where the face is a wall or the velocity is parallel to it).
+template <int P>
+__device__ __forceinline__ void row_traces(const StageArgs &a, int qg, int k, int nbx, int nby,
+                                           double (&px)[P + 1], double (&py)[P + 1]) {
+  constexpr int N1 = P + 1, NP = N1 * N1;
+  const double cx = a.vel[qg], cy = a.vel[a.Q + qg];
+  const bool gx = cx != 0.0 && nbx >= 0, gy = cy != 0.0 && nby >= 0;
+  const double *sx = a.fs + ((size_t)(nbx >= 0 ? nbx : 0) * a.Q + qg) * NP + (cx > 0.0 ? P : 0);
+  const double *sy = a.fs + ((size_t)(nby >= 0 ? nby : 0) * a.Q + qg) * NP + (cy > 0.0 ? N1 * P : 0);
+  load_face_traces<N1, N1>(sx, sy, gx, gy, px, py);
+  (void)k;
+}
+
+// As row_traces, with 32-bit offsets from the base of f_s.
+template <int P>
+__device__ __forceinline__ void row_traces32(const StageArgs &a, double cx, double cy, int qg, int nbx,
+                                             int nby, double (&px)[P + 1], double (&py)[P + 1]) {
+  constexpr int N1 = P + 1, NP = N1 * N1;
+  const bool gx = cx != 0.0 && nbx >= 0, gy = cy != 0.0 && nby >= 0;
+  const uint32_t ox = ((uint32_t)(nbx >= 0 ? nbx : 0) * a.Q + qg) * NP + (cx > 0.0 ? P : 0);
+  const uint32_t oy = ((uint32_t)(nby >= 0 ? nby : 0) * a.Q + qg) * NP + (cy > 0.0 ? N1 * P : 0);
+#pragma unroll
+  for (int m = 0; m < N1; ++m) px[m] = gx ? ld32<double>(a.fs, ox + N1 * m) : 0.0;
+  if (N1 % 2 == 0) {
+#pragma unroll
+    for (int m = 0; m < N1; m += 2) {
+      double2v v = {0.0, 0.0};
+      if (gy) v = ld32<double2v>(a.fs, oy + m);
+      py[m] = v[0];
+      py[m + 1] = v[1];
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < N1; ++m) py[m] = gy ? ld32<double>(a.fs, oy + m) : 0.0;
+  }
+}
+
+// L(f) of one (velocity, element) row held in LDS: its NP nodal values go to
+// registers; the derivative and lift tables are wave-uniform scalars.  mm is
+// the element's moment table, rwe its wall densities ([face][NFP]).  The
+// result overwrites the row.
+// RowVel: the velocity data of one row (e_x, e_y, w and the wall exterior
+// states f^eq(1, u_b) of its two inflow faces).
+struct RowVel {
+  double cx, cy, wq, gbx, gby;
+};
+
+__device__ __forceinline__ RowVel row_vel(const StageArgs &a, int qg) {
+  RowVel v;
+  v.cx = a.vel[qg];
+  v.cy = a.vel[a.Q + qg];
+  v.wq = a.vel[2 * a.Q + qg];
+  v.gbx = a.feqb[(v.cx > 0.0 ? 3 : 1) * a.Q + qg];
+  v.gby = a.feqb[(v.cy > 0.0 ? 0 : 2) * a.Q + qg];
+  return v;
+}
+
+template <int P>
+__device__ __forceinline__ void row_rhs(const StageArgs &a, double *row, const double *mm,
+                                        const double *rwe, const RowVel &rv, int nbx, int nby,
+                                        const double (&px)[P + 1], const double (&py)[P + 1]) {
+  using Sh = Shape<P>;
+  constexpr int N1 = Sh::N1, NP = Sh::NP, NFP = Sh::NFP;
+  const double cx = rv.cx, cy = rv.cy, wq = rv.wq;
+  const int fxc = cx > 0.0 ? 3 : 1, fyc = cy > 0.0 ? 0 : 2;  // inflow faces
+  double f[NP];
+  if (Sh::VEC) {
+#pragma unroll
+    for (int c = 0; c < NP / 2; ++c) {
+      const double2v v = *reinterpret_cast<const double2v *>(row + 2 * c);
+      f[2 * c] = v[0];
+      f[2 * c + 1] = v[1];
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < NP; ++c) f[c] = row[c];
+  }
+  double kk[NP];
+  const double ax = cx * a.rx, ay = cy * a.sy;
+#pragma unroll
+  for (int j = 0; j < N1; ++j)
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+      double dr = 0.0, ds = 0.0;
+#pragma unroll
+      for (int m = 0; m < N1; ++m) {
+        dr += a.D1[i * N1 + m] * f[m + N1 * j];
+        ds += a.D1[j * N1 + m] * f[i + N1 * m];
+      }
+      kk[i + N1 * j] = -(ax * dr + ay * ds);
+    }
+  if (cx != 0.0) {
+    const double wx = a.fsx * (-fabs(cx));
+    const double gbx = rv.gbx;
+    const double *rwx = rwe + fxc * NFP;
+#pragma unroll
+    for (int jj = 0; jj < N1; ++jj) {
+      const double own = cx > 0.0 ? f[N1 * jj] : f[N1 * jj + P];
+      const double ext = nbx >= 0 ? px[jj] : rwx[jj] * gbx;
+      const double J = wx * (own - ext);
+#pragma unroll
+      for (int ii = 0; ii < N1; ++ii) kk[ii + N1 * jj] += (cx > 0.0 ? a.lift_lo[ii] : a.lift_hi[ii]) * J;
+    }
+  }
+  if (cy != 0.0) {
+    const double wy = a.fsy * (-fabs(cy));
+    const double gby = rv.gby;
+    const double *rwy = rwe + fyc * NFP;
+#pragma unroll
+    for (int ii = 0; ii < N1; ++ii) {
+      const double own = cy > 0.0 ? f[ii] : f[ii + N1 * P];
+      const double ext = nby >= 0 ? py[ii] : rwy[ii] * gby;
+      const double J = wy * (own - ext);
+#pragma unroll
+      for (int jj = 0; jj < N1; ++jj) kk[ii + N1 * jj] += (cy > 0.0 ? a.lift_lo[jj] : a.lift_hi[jj]) * J;
+    }
+  }
+#pragma unroll
+  for (int nn = 0; nn < NP; ++nn) {
+    const double4v m4 = *reinterpret_cast<const double4v *>(mm + 4 * nn);
+    const double eu = cx * m4[0] + cy * m4[1];
+    const double feq = wq * m4[2] * (m4[3] + eu * (a.theta_inv + eu * a.half_theta2_inv));
+    kk[nn] += (feq - f[nn]) * a.inv_tau;
+  }
+  if (Sh::VEC) {
+#pragma unroll
+    for (int c = 0; c < NP / 2; ++c)
+      *reinterpret_cast<double2v *>(row + 2 * c) = double2v{kk[2 * c], kk[2 * c + 1]};
+  } else {
+#pragma unroll
+    for (int c = 0; c < NP; ++c) row[c] = kk[c];
+  }
+}
+
 // MODE: 0 writes L(f_s); 1 first RK4 stage; 2 second and third; 4 fourth.
+// One work-group per (element block, velocity tile); the general kernel.
 template <int P, int MODE>
 __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
   using Sh = Shape<P>;
-  constexpr int N1 = Sh::N1, NP = Sh::NP, NFP = Sh::NFP, S = Sh::S;
+  constexpr int NP = Sh::NP, NFP = Sh::NFP, S = Sh::S;
   constexpr int CW = Sh::VEC ? 2 : 1;  // doubles per global access
   constexpr int CPE = NP / CW;         // accesses per element per velocity
   constexpr int U = 8;                 // global accesses in flight per thread
-  constexpr int NB = (NP + 15) / 16;   // 16-node column blocks of the moment product
   using V = typename std::conditional<Sh::VEC, double2v, double>::type;
   extern __shared__ double lds[];
   const int E = a.E, log2E = a.log2E;
@@ -172,13 +472,10 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
   const int q0 = blockIdx.y * a.Qt;
   const int Qb = min(a.Qt, a.Q - q0);
   const int rows = Qb * E;  // LDS row r = q_local * E + e
-  const int cpr = E * CPE;  // accesses per velocity row of the block
-  const int nch = Qb * cpr;
-  const size_t KNP = (size_t)a.K * NP;
-  const size_t boff = (size_t)q0 * KNP + (size_t)k0 * NP;  // block origin in f
-  const double *vex = a.vel;
-  const double *vey = a.vel + a.Q;
-  const double *vw = a.vel + 2 * a.Q;
+  const int nch = rows * CPE;
+  const size_t KN = (size_t)a.K * NP;
+  const size_t QNP = (size_t)a.Q * NP;
+  const size_t boff = (size_t)k0 * QNP + (size_t)q0 * NP;  // tile origin in f
 
   // ---- 0. neighbours of the block's elements (-1: wall) -----------------------
   if (tid < E * 4) {
@@ -197,106 +494,31 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
       for (int u = 0; u < U; ++u) {
         const int c = c0 + u * nthr;
         int q, e, w;
-        split_access<CPE>(c, cpr, log2E, q, e, w);
-        if (all || (c < nch && e < Eb)) v[u] = *reinterpret_cast<const V *>(src + (size_t)q * KNP + CW * w);
+        split_access<CPE>(c, Qb, E, q, e, w);
+        if (all || (c < nch && e < Eb)) v[u] = *reinterpret_cast<const V *>(src + e * QNP + q * NP + CW * w);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int c = c0 + u * nthr;
         int q, e, w;
-        split_access<CPE>(c, cpr, log2E, q, e, w);
-        if (all || (c < nch && e < Eb)) lds_put(tile + (q * E + e) * S + CW * (w - e * CPE), v[u]);
+        split_access<CPE>(c, Qb, E, q, e, w);
+        if (all || (c < nch && e < Eb)) lds_put(tile + (q * E + e) * S + CW * w, v[u]);
       }
     }
   }
   __syncthreads();
 
   // ---- 2. node moments and diffuse-wall densities ----------------------------
-  // C[c][n] = sum_q W[q][c] f[q][n] with W[q] = (1, e_x, e_y, outgoing normal
-  // speed at the bottom, right, top, left wall): a dense (7 x Q) x (Q x NP)
-  // product per element, on FP64 matrix cores (16x16x4 steps; K split over
-  // the four wavefronts, partial products summed through LDS).
-  const bool walls = a.wall_mask != 0;
   if (a.fused) {
-    const int wave = tid >> 6, lane = tid & 63;
-    const int tasks = E * NB;                     // (element, 16-node block)
-    const int ks = tasks >= 4 ? 1 : 4 / tasks;    // K slices per task
-    const int qper = ((Qb + ks - 1) / ks + 3) / 4 * 4;
-    for (int pr = wave; pr < tasks * ks; pr += nthr >> 6) {
-      const int t = pr / ks, sl = pr % ks;
-      const int e = t / NB, nb = t % NB;
-      const int node = nb * 16 + (lane & 15);
-      const int qa = sl * qper, qe = min(Qb, qa + qper);
-      double4v acc = {0.0, 0.0, 0.0, 0.0}, acc1 = acc, acc2 = acc, acc3 = acc;
-      if (e < Eb) {
-        constexpr int KB = 16;  // 4-velocity steps whose operands are loaded together
-        for (int qb = qa; qb < qe; qb += 4 * KB) {
-          double av[KB], bv[KB];
-#pragma unroll
-          for (int t = 0; t < KB; ++t) {
-            const int q = qb + 4 * t + (lane >> 4);
-            const bool in = q < qe;
-            av[t] = in ? a.wmom[(size_t)(q0 + q) * 16 + (lane & 15)] : 0.0;
-            bv[t] = (in && node < NP) ? tile[(q * E + e) * S + node] : 0.0;
-          }
-#pragma unroll
-          for (int t = 0; t < KB; t += 4) {  // four independent accumulation chains
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t + 1], bv[t + 1], acc1, 0, 0, 0);
-            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t + 2], bv[t + 2], acc2, 0, 0, 0);
-            acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t + 3], bv[t + 3], acc3, 0, 0, 0);
-          }
-        }
-      }
-      acc += acc1 + acc2 + acc3;
-      // register v of a lane holds C[4 v + lane / 16][lane % 16]; rows 0..6 are used
-      if (node < NP) {
-        double *pp = part + ((size_t)pr * 7) * 16;
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-          const int row = 4 * v + (lane >> 4);
-          if (row < 7) pp[row * 16 + (lane & 15)] = acc[v];
-        }
-      }
-    }
+    block_moments_mfma<P, 16>(tile, part, a.wmom + (size_t)q0 * 16, E, Qb, Eb, tid, nthr);
     __syncthreads();
-    if (tid < E * NP) {
-      const int e2 = tid / NP, n2 = tid % NP;
-      if (e2 < Eb) {
-        const int t = e2 * NB + n2 / 16, col = n2 % 16;
-        double sm[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int sl = 0; sl < ks; ++sl) {
-          const double *pp = part + ((size_t)(t * ks + sl) * 7) * 16;
-#pragma unroll
-          for (int c = 0; c < 7; ++c) sm[c] += pp[c * 16 + col];
-        }
-        const double rho = sm[0], ux = sm[1] / rho, uy = sm[2] / rho;
-        double *m = mom + (e2 * NP + n2) * 4;
-        m[0] = ux;
-        m[1] = uy;
-        m[2] = rho;
-        m[3] = 1.0 - (ux * ux + uy * uy) * a.half_theta_inv;
-        if (walls) {
-          const int i2 = n2 % N1, j2 = n2 / N1;
-          const bool on[4] = {nbr[e2 * 4 + 0] < 0 && j2 == 0, nbr[e2 * 4 + 1] < 0 && i2 == P,
-                              nbr[e2 * 4 + 2] < 0 && j2 == P, nbr[e2 * 4 + 3] < 0 && i2 == 0};
-          const int fm[4] = {i2, j2, i2, j2};
-#pragma unroll
-          for (int fc = 0; fc < 4; ++fc)
-            if (on[fc]) {
-              const double v = sm[3 + fc] * a.wall_den_inv[fc];
-              rw[(e2 * 4 + fc) * NFP + fm[fc]] = v;
-              if (a.rhow_out) a.rhow_out[((size_t)(k0 + e2) * 4 + fc) * NFP + fm[fc]] = v;
-            }
-        }
-      }
-    }
+    block_moments_combine<P>(a, part, mom, rw, nbr, E, Eb, k0, tid);
   } else {
     if (tid < E * NP) {
       const int e2 = tid / NP, n2 = tid % NP;
       if (e2 < Eb) {
         const size_t node = (size_t)(k0 + e2) * NP + n2;
-        const double rho = a.mom[node], ux = a.mom[KNP + node], uy = a.mom[2 * KNP + node];
+        const double rho = a.mom[node], ux = a.mom[KN + node], uy = a.mom[2 * KN + node];
         double *m = mom + (e2 * NP + n2) * 4;
         m[0] = ux;
         m[1] = uy;
@@ -304,7 +526,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
         m[3] = 1.0 - (ux * ux + uy * uy) * a.half_theta_inv;
       }
     }
-    if (walls) {
+    if (a.wall_mask != 0) {
       for (int u = tid; u < E * 4 * NFP; u += nthr) {
         const int e2 = u / (4 * NFP);
         if (e2 < Eb) rw[u] = a.rhow[(size_t)(k0 + e2) * 4 * NFP + (u - e2 * 4 * NFP)];
@@ -314,92 +536,15 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
   __syncthreads();
 
   // ---- 3. per velocity row: L(f) = volume + lifted inflow jumps + collision ----
-  // A thread owns one (velocity, element) row: its NP nodal values live in
-  // registers; the derivative and lift tables are wave-uniform scalars.
   for (int r = tid; r < rows; r += nthr) {
     const int q = r >> log2E, e = r & (E - 1);
     if (e >= Eb) continue;
     const int qg = q0 + q;
-    const double cx = vex[qg], cy = vey[qg], wq = vw[qg];
-    // exterior traces of the two inflow faces (their loads overlap the volume term)
-    const int nbx = nbr[e * 4 + (cx > 0.0 ? 3 : 1)], nby = nbr[e * 4 + (cy > 0.0 ? 0 : 2)];
-    const double gbx = a.feqb[(cx > 0.0 ? 3 : 1) * a.Q + qg], gby = a.feqb[(cy > 0.0 ? 0 : 2) * a.Q + qg];
+    const RowVel rv = row_vel(a, qg);
+    const int nbx = nbr[e * 4 + (rv.cx > 0.0 ? 3 : 1)], nby = nbr[e * 4 + (rv.cy > 0.0 ? 0 : 2)];
     double px[NFP], py[NFP];
-    {
-      const bool gx = cx != 0.0 && nbx >= 0, gy = cy != 0.0 && nby >= 0;
-      const double *sx = a.fs + (size_t)qg * KNP + (size_t)(nbx >= 0 ? nbx : 0) * NP + (cx > 0.0 ? P : 0);
-      const double *sy = a.fs + (size_t)qg * KNP + (size_t)(nby >= 0 ? nby : 0) * NP + (cy > 0.0 ? N1 * P : 0);
-      load_face_traces<N1, NFP>(sx, sy, gx, gy, px, py);
-    }
-    // inflow faces of this velocity
-    const int fxc = cx > 0.0 ? 3 : 1, fyc = cy > 0.0 ? 0 : 2;
-    double f[NP];
-    double *row = tile + r * S;
-    if (Sh::VEC) {
-#pragma unroll
-      for (int c = 0; c < NP / 2; ++c) {
-        const double2v v = *reinterpret_cast<const double2v *>(row + 2 * c);
-        f[2 * c] = v[0];
-        f[2 * c + 1] = v[1];
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < NP; ++c) f[c] = row[c];
-    }
-    double kk[NP];
-    const double ax = cx * a.rx, ay = cy * a.sy;
-#pragma unroll
-    for (int j = 0; j < N1; ++j)
-#pragma unroll
-      for (int i = 0; i < N1; ++i) {
-        double dr = 0.0, ds = 0.0;
-#pragma unroll
-        for (int m = 0; m < N1; ++m) {
-          dr += a.D1[i * N1 + m] * f[m + N1 * j];
-          ds += a.D1[j * N1 + m] * f[i + N1 * m];
-        }
-        kk[i + N1 * j] = -(ax * dr + ay * ds);
-      }
-    if (cx != 0.0) {
-      const double wx = a.fsx * (-fabs(cx));
-      const double *rwx = rw + (e * 4 + fxc) * NFP;
-#pragma unroll
-      for (int jj = 0; jj < N1; ++jj) {
-        const double own = cx > 0.0 ? f[N1 * jj] : f[N1 * jj + P];
-        const double ext = nbx >= 0 ? px[jj] : rwx[jj] * gbx;
-        const double J = wx * (own - ext);
-#pragma unroll
-        for (int ii = 0; ii < N1; ++ii) kk[ii + N1 * jj] += (cx > 0.0 ? a.lift_lo[ii] : a.lift_hi[ii]) * J;
-      }
-    }
-    if (cy != 0.0) {
-      const double wy = a.fsy * (-fabs(cy));
-      const double *rwy = rw + (e * 4 + fyc) * NFP;
-#pragma unroll
-      for (int ii = 0; ii < N1; ++ii) {
-        const double own = cy > 0.0 ? f[ii] : f[ii + N1 * P];
-        const double ext = nby >= 0 ? py[ii] : rwy[ii] * gby;
-        const double J = wy * (own - ext);
-#pragma unroll
-        for (int jj = 0; jj < N1; ++jj) kk[ii + N1 * jj] += (cy > 0.0 ? a.lift_lo[jj] : a.lift_hi[jj]) * J;
-      }
-    }
-    const double *mm = mom + e * NP * 4;
-#pragma unroll
-    for (int nn = 0; nn < NP; ++nn) {
-      const double4v m4 = *reinterpret_cast<const double4v *>(mm + 4 * nn);
-      const double eu = cx * m4[0] + cy * m4[1];
-      const double feq = wq * m4[2] * (m4[3] + eu * (a.theta_inv + eu * a.half_theta2_inv));
-      kk[nn] += (feq - f[nn]) * a.inv_tau;
-    }
-    if (Sh::VEC) {
-#pragma unroll
-      for (int c = 0; c < NP / 2; ++c)
-        *reinterpret_cast<double2v *>(row + 2 * c) = double2v{kk[2 * c], kk[2 * c + 1]};
-    } else {
-#pragma unroll
-      for (int c = 0; c < NP; ++c) row[c] = kk[c];
-    }
+    row_traces<P>(a, qg, k0 + e, nbx, nby, px, py);
+    row_rhs<P>(a, tile + r * S, mom + e * NP * 4, rw + e * 4 * NFP, rv, nbx, nby, px, py);
   }
   __syncthreads();
 
@@ -418,10 +563,10 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
     for (int u = 0; u < U; ++u) {
       const int c = c0 + u * nthr;
       int q, e, w;
-      split_access<CPE>(c, cpr, log2E, q, e, w);
+      split_access<CPE>(c, Qb, E, q, e, w);
       ok[u] = all || (c < nch && e < Eb);
-      go[u] = (size_t)q * KNP + CW * w;
-      if (ok[u]) kv[u] = lds_get<V>(tile + (q * E + e) * S + CW * (w - e * CPE));
+      go[u] = e * QNP + q * NP + CW * w;
+      if (ok[u]) kv[u] = lds_get<V>(tile + (q * E + e) * S + CW * w);
     }
     if (MODE != 0) {
 #pragma unroll
@@ -444,6 +589,215 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
   }
 }
 
+// LDS layout of the pipelined kernel, in doubles: three f tiles (staged,
+// computed, updated), two trace buffers (staged, computed), then the moment
+// scratch of the block being computed.
+struct PipeLayout {
+  int tile, trace, part, mom, rw, nbr, total;
+};
+
+__host__ __device__ inline PipeLayout pipe_layout(int NP, int NFP, int S, int E, int Q) {
+  PipeLayout L;
+  L.tile = Q * E * S;
+  L.trace = Q * E * (2 * NFP + 1);  // odd row stride: 8-byte accesses without bank conflicts
+  const int tasks = E * ((NP + 15) / 16);
+  const int pairs = tasks >= 4 ? tasks : 4;
+  L.part = 3 * L.tile + 2 * L.trace;
+  L.mom = (L.part + pairs * 7 * 16 + 3) / 4 * 4;  // 32-byte aligned (read as double4)
+  L.rw = L.mom + E * NP * 4;
+  L.nbr = L.rw + E * 4 * NFP;
+  L.total = L.nbr + (E * 4 + 1) / 2;
+  return L;
+}
+
+// Loads a memory thread of the pipelined kernel issues in iteration t - 1
+// for iteration t: the f tile and the row's inflow traces of the block staged
+// in t (index t of the run) and the RK operands of the block updated in t
+// (index t - 2).
+template <int P, int MODE, int PF, typename V>
+__device__ __forceinline__ void pipe_issue(const StageArgs &a, int t, int first, int nl, int nb,
+                                           int tid, double cx, double cy, V (&tl)[PF], V (&x)[PF],
+                                           V (&y)[PF], double (&px)[P + 1], double (&py)[P + 1]) {
+  using Sh = Shape<P>;
+  constexpr int NP = Sh::NP;
+  constexpr int CW = Sh::VEC ? 2 : 1;
+  constexpr int CPE = NP / CW;
+  const int E = a.E, Q = a.Q, rows = Q * E, nch = rows * CPE;
+  const uint32_t QNP = (uint32_t)Q * NP;
+  const int rq = tid >> a.log2E, re = tid & (E - 1);
+  if (t < nb) {
+    const int bs = first + t * nl, Ebs = min(E, a.K - bs * E);
+    load_tile<CPE, CW, NP, PF>(tl, a.fs + (size_t)bs * E * QNP, tid, kBlock, nch, Q, E, Ebs, QNP);
+    if (tid < rows && re < Ebs) {
+      const int nbx = neighbour(bs * E + re, cx > 0.0 ? 3 : 1, a);
+      const int nby = neighbour(bs * E + re, cy > 0.0 ? 0 : 2, a);
+      row_traces32<P>(a, cx, cy, rq, nbx, nby, px, py);
+    }
+  }
+  if (MODE != 0 && t >= 2 && t - 2 < nb) {
+    const int bu = first + (t - 2) * nl, Ebu = min(E, a.K - bu * E);
+    const size_t boff = (size_t)bu * E * QNP;
+    const double *xr = (MODE == 1 ? a.fs : MODE == 2 ? a.fn : a.acc) + boff;
+    const double *yr = a.acc + boff;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int c = tid + u * kBlock;
+      int q, e, w;
+      split_access<CPE>(c, Q, E, q, e, w);
+      if (c < nch && e < Ebu) {
+        const uint32_t go = (uint32_t)e * QNP + (uint32_t)(q * NP + CW * w);
+        x[u] = ld32<V>(xr, go);
+        if (MODE == 2) y[u] = ld32<V>(yr, go);
+      }
+    }
+  }
+}
+
+// Persistent, wave-specialised form of the fused stage, for blocks whose
+// velocity rows fit one per thread and whose f tile fits kStreamDoubles
+// doubles per thread.  A work-group of 2 x kBlock threads walks a run of
+// element blocks as a three-deep pipeline: in iteration t its four memory
+// wavefronts put the f tile and the inflow traces of block t into LDS, apply
+// the RK4 update of block t-2 and issue the loads of iteration t+1, so that
+// every load has a whole iteration to arrive, while its four compute
+// wavefronts reduce the moments of block t-1 on the matrix cores and
+// evaluate L(f) of its rows.  HBM traffic and the LDS /
+// register work of neighbouring blocks thus overlap inside each work-group.
+// Blocks are dealt to the XCDs (work-group w runs on XCD w mod 8) in
+// contiguous runs, so the neighbour traces are mostly read from that XCD's
+// L2.  The arithmetic per block is that of stage_kernel, in the same order.
+template <int P, int MODE>
+__global__ __launch_bounds__(2 * kBlock) void pipe_kernel(const StageArgs a) {
+  using Sh = Shape<P>;
+  constexpr int NP = Sh::NP, NFP = Sh::NFP, S = Sh::S, TS = 2 * NFP + 1;
+  constexpr int CW = Sh::VEC ? 2 : 1;
+  constexpr int CPE = NP / CW;
+  constexpr int PF = kStreamDoubles / CW;  // tile accesses per memory thread
+  using V = typename std::conditional<Sh::VEC, double2v, double>::type;
+  extern __shared__ double lds[];
+  const int E = a.E, log2E = a.log2E, Q = a.Q;
+  const PipeLayout L = pipe_layout(NP, NFP, S, E, Q);
+  double *part = lds + L.part;
+  double *mom = lds + L.mom;
+  double *rw = lds + L.rw;
+  int *nbr = (int *)(lds + L.nbr);
+  const int rows = Q * E, nch = rows * CPE;
+  const uint32_t QNP = (uint32_t)Q * NP;
+
+  // block run of this work-group: the blocks are split into contiguous runs,
+  // one per XCD that has work-groups, and the work-groups of an XCD take
+  // every nl-th block of its run
+  const int nx8 = min(8, (int)gridDim.x);
+  const int xcd = blockIdx.x & 7, l = blockIdx.x >> 3;
+  const int nl = ((int)gridDim.x - xcd + 7) >> 3;  // work-groups on this XCD
+  const int per = a.nblk / nx8, rem = a.nblk - per * nx8;
+  const int b1 = xcd * per + min(xcd, rem) + per + (xcd < rem ? 1 : 0);
+  const int first = xcd * per + min(xcd, rem) + l;
+  if (first >= b1) return;
+  const int nb = (b1 - first + nl - 1) / nl;  // blocks of this work-group
+  const bool memory = threadIdx.x >= kBlock;  // wavefronts 4..7
+
+  // The memory wavefronts' gather addresses depend on the velocity of the
+  // thread's row: it is loaded once, since a global load inside the loop would
+  // make the gathers wait for every load issued before it (loads complete in
+  // order).
+  const int tid0 = (int)(threadIdx.x & (kBlock - 1));
+  const int rq0 = min(tid0 >> log2E, Q - 1);
+  double mcx = 0.0, mcy = 0.0;
+  if (memory) {
+    mcx = a.vel[rq0];
+    mcy = a.vel[Q + rq0];
+  }
+
+  // operands in flight from one iteration to the next (memory wavefronts)
+  V tl[PF], x[PF], y[PF];
+  double px[NFP], py[NFP];
+  if (memory) pipe_issue<P, MODE, PF>(a, 0, first, nl, nb, tid0, mcx, mcy, tl, x, y, px, py);
+
+  for (int t = 0; t < nb + 2; ++t) {
+    // The thread index is made opaque once per iteration so that the
+    // per-access index arithmetic is recomputed rather than held in
+    // registers across the loop.
+    int tid = (int)(threadIdx.x & (kBlock - 1));
+    asm volatile("" : "+v"(tid));
+    const int bs = first + t * nl;  // block staged in this iteration
+    const int bc = bs - nl;         // block computed
+    const int bu = bs - 2 * nl;     // block updated
+    const bool do_s = t < nb, do_c = t >= 1 && t <= nb, do_u = t >= 2;
+    const int Ebs = min(E, a.K - bs * E), Ebc = min(E, a.K - bc * E), Ebu = min(E, a.K - bu * E);
+    double *tile_s = lds + (t % 3) * L.tile;
+    double *tile_c = lds + ((t + 2) % 3) * L.tile;
+    double *tile_u = lds + ((t + 1) % 3) * L.tile;
+    double *trace_s = lds + 3 * L.tile + (t & 1) * L.trace;
+    const double *trace_c = lds + 3 * L.tile + ((t + 1) & 1) * L.trace;
+    const int rq = tid >> log2E, re = tid & (E - 1);
+
+    // A. compute: moment partials (the memory wavefronts' loads are in flight)
+    if (!memory && do_c) {
+      if (tid < E * 4) {
+        const int e = tid >> 2, fc = tid & 3;
+        nbr[tid] = e < Ebc ? neighbour(bc * E + e, fc, a) : -1;
+      }
+      block_moments_mfma<P, 8>(tile_c, part, a.wmom, E, Q, Ebc, tid, kBlock);
+    }
+    __syncthreads();
+    if (!memory && do_c) block_moments_combine<P>(a, part, mom, rw, nbr, E, Ebc, bc * E, tid);
+    __syncthreads();
+
+    // C. memory: the staged tile and traces into LDS, the RK4 update of block
+    // bu; compute: L(f) of the rows of block bc
+    if (memory) {
+      if (do_s) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          const int c = tid + u * kBlock;
+          int q, e, w;
+          split_access<CPE>(c, Q, E, q, e, w);
+          if (c < nch && e < Ebs) lds_put(tile_s + (q * E + e) * S + CW * w, tl[u]);
+        }
+        if (tid < rows && re < Ebs) {
+          double *tr = trace_s + tid * TS;
+#pragma unroll
+          for (int m = 0; m < NFP; ++m) {
+            tr[m] = px[m];
+            tr[NFP + m] = py[m];
+          }
+        }
+      }
+      if (do_u) {
+        const size_t boff = (size_t)bu * E * QNP;
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          const int c = tid + u * kBlock;
+          int q, e, w;
+          split_access<CPE>(c, Q, E, q, e, w);
+          if (c < nch && e < Ebu) {
+            const V kv = lds_get<V>(tile_u + (q * E + e) * S + CW * w);
+            const uint32_t go = (uint32_t)e * QNP + (uint32_t)(q * NP + CW * w);
+            V o, an;
+            rk_update<MODE>(kv, x[u], y[u], a.c_acc, a.c_out, o, an);
+            st32<V>(a.out + boff, go, o);
+            if (MODE == 1 || MODE == 2) st32<V>(a.acc + boff, go, an);
+          }
+        }
+      }
+      pipe_issue<P, MODE, PF>(a, t + 1, first, nl, nb, tid, mcx, mcy, tl, x, y, px, py);
+    } else if (do_c && tid < rows && re < Ebc) {
+      const RowVel rv = row_vel(a, rq);
+      const int nbx = nbr[re * 4 + (rv.cx > 0.0 ? 3 : 1)], nby = nbr[re * 4 + (rv.cy > 0.0 ? 0 : 2)];
+      double qx[NFP], qy[NFP];
+      const double *tr = trace_c + tid * TS;
+#pragma unroll
+      for (int m = 0; m < NFP; ++m) {
+        qx[m] = tr[m];
+        qy[m] = tr[NFP + m];
+      }
+      row_rhs<P>(a, tile_c + tid * S, mom + re * NP * 4, rw + re * 4 * NFP, rv, nbx, nby, qx, qy);
+    }
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(256) void moments_kernel(const double *f, const double *vel, int K,
                                                       int P, int Q, int nx, int ny, int wall_mask,
                                                       double d0, double d1, double d2, double d3,
@@ -462,7 +816,7 @@ __global__ __launch_bounds__(256) void moments_kernel(const double *f, const dou
   const bool anyw = wb || wr || wt || wl;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, hb = 0.0, hr = 0.0, ht = 0.0, hl = 0.0;
   for (int q = 0; q < Q; ++q) {
-    const double v = f[(size_t)q * KNP + i];
+    const double v = f[((size_t)k * Q + q) * NP + n];
     const double cx = vel[q], cy = vel[Q + q];
     s0 += v;
     s1 += cx * v;
@@ -488,7 +842,7 @@ __global__ __launch_bounds__(256) void moments_kernel(const double *f, const dou
 __device__ inline double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
 
 __global__ __launch_bounds__(256) void residual_kernel(const double *k, const double *vel, int KNP,
-                                                       int Q, double scale,
+                                                       int Np, int Q, double scale,
                                                        unsigned long long *result) {
   __shared__ double red[256 / 64];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -496,7 +850,7 @@ __global__ __launch_bounds__(256) void residual_kernel(const double *k, const do
   if (i < KNP) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int q = 0; q < Q; ++q) {
-      const double v = k[(size_t)q * KNP + i];
+      const double v = k[((size_t)(i / Np) * Q + q) * Np + i % Np];
       s0 += v;
       s1 += vel[q] * v;
       s2 += vel[Q + q] * v;
@@ -514,15 +868,27 @@ __global__ __launch_bounds__(256) void residual_kernel(const double *k, const do
   }
 }
 
-__global__ void init_equilibrium_kernel(double *f, const double *vel, size_t KNP, int Q,
+__global__ void init_equilibrium_kernel(double *f, const double *vel, size_t KNP, int Np, int Q,
                                         double rho0, double ux0, double uy0, double theta) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int q = blockIdx.y;
   if (i >= KNP) return;
   const double cx = vel[q], cy = vel[Q + q], w = vel[2 * Q + q];
   const double eu = cx * ux0 + cy * uy0, usq = ux0 * ux0 + uy0 * uy0;
-  f[(size_t)q * KNP + i] =
+  f[((i / Np) * Q + q) * Np + i % Np] =
       w * rho0 * (1.0 + eu / theta + eu * eu / (2.0 * theta * theta) - usq / (2.0 * theta));
+}
+
+// f[q][k][n] <-> f[k][q][n] (to_element_major selects the direction).
+__global__ void transpose_kernel(const double *src, double *dst, size_t KNP, int Np, int Q,
+                                 int to_element_major) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // k * Np + n
+  const int q = blockIdx.y;
+  if (i >= KNP) return;
+  const size_t qmaj = (size_t)q * KNP + i;
+  const size_t emaj = ((i / Np) * Q + q) * Np + i % Np;
+  if (to_element_major) dst[emaj] = src[qmaj];
+  else dst[qmaj] = src[emaj];
 }
 
 __global__ void fill_u64_kernel(unsigned long long *p, size_t n, unsigned long long v) {
@@ -548,6 +914,29 @@ hipError_t launch_stage_pm(const StageArgs &a, size_t lds, int ntiles, hipStream
 
 
 
+template <int P, int MODE>
+hipError_t launch_stream_pm(const StageArgs &a, size_t lds, int groups, hipStream_t st) {
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void *)pipe_kernel<P, MODE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((pipe_kernel<P, MODE>), dim3((unsigned)groups), dim3(2 * kBlock), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_stream_p(const StageArgs &a, size_t lds, int groups, hipStream_t st) {
+  switch (a.stage) {
+    case 0: return launch_stream_pm<P, 0>(a, lds, groups, st);
+    case 1: return launch_stream_pm<P, 1>(a, lds, groups, st);
+    case 2:
+    case 3: return launch_stream_pm<P, 2>(a, lds, groups, st);
+    case 4: return launch_stream_pm<P, 4>(a, lds, groups, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int P>
 hipError_t launch_stage_p(const StageArgs &a, size_t lds, int ntiles, hipStream_t st) {
   switch (a.stage) {
@@ -566,6 +955,30 @@ size_t stage_lds_bytes(int p, int E, int Qt) {
   const int N1 = p + 1, NP = N1 * N1;
   const int S = (NP % 2 == 0) ? NP + 2 : NP;
   return (size_t)lds_layout(NP, N1, S, E, Qt).total * sizeof(double);
+}
+
+bool stream_applicable(int p, int E, int Q, int64_t K) {
+  const int NP = (p + 1) * (p + 1);
+  return p >= 1 && p <= kStreamMaxP && (int64_t)E * Q <= kBlock &&
+         (int64_t)E * Q * NP <= (int64_t)kStreamDoubles * kBlock &&
+         (int64_t)Q * K * NP * 8 < ((int64_t)1 << 32);
+}
+
+size_t stream_lds_bytes(int p, int E, int Q) {
+  const int N1 = p + 1, NP = N1 * N1;
+  const int S = (NP % 2 == 0) ? NP + 2 : NP;
+  return (size_t)pipe_layout(NP, N1, S, E, Q).total * sizeof(double);
+}
+
+hipError_t launch_stream(int p, const StageArgs &a, size_t lds, int groups, hipStream_t st) {
+  if (!a.fused || !stream_applicable(p, a.E, a.Q, a.K) || groups < 1 || groups > a.nblk)
+    return hipErrorInvalidValue;
+  switch (p) {
+    case 1: return launch_stream_p<1>(a, lds, groups, st);
+    case 2: return launch_stream_p<2>(a, lds, groups, st);
+    case 3: return launch_stream_p<3>(a, lds, groups, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_stage(int p, const StageArgs &a, size_t lds, int ntiles, hipStream_t st) {
@@ -596,7 +1009,7 @@ hipError_t launch_residual(const double *k, const double *vel, int K, int Np, in
                            unsigned long long *result, hipStream_t st) {
   const int KNP = K * Np;
   const unsigned nb = (unsigned)((KNP + 255) / 256);
-  hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(256), 0, st, k, vel, KNP, Q, scale, result);
+  hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(256), 0, st, k, vel, KNP, Np, Q, scale, result);
   return hipGetLastError();
 }
 
@@ -604,8 +1017,17 @@ hipError_t launch_init_equilibrium(double *f, const double *vel, int K, int Np, 
                                    double ux0, double uy0, double theta, hipStream_t st) {
   const size_t KNP = (size_t)K * Np;
   dim3 grid((unsigned)((KNP + 255) / 256), (unsigned)Q);
-  hipLaunchKernelGGL(init_equilibrium_kernel, grid, dim3(256), 0, st, f, vel, KNP, Q, rho0, ux0,
+  hipLaunchKernelGGL(init_equilibrium_kernel, grid, dim3(256), 0, st, f, vel, KNP, Np, Q, rho0, ux0,
                      uy0, theta);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double *src, double *dst, int K, int Np, int Q,
+                            int to_element_major, hipStream_t st) {
+  const size_t KNP = (size_t)K * Np;
+  dim3 grid((unsigned)((KNP + 255) / 256), (unsigned)Q);
+  hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, st, src, dst, KNP, Np, Q,
+                     to_element_major);
   return hipGetLastError();
 }
 

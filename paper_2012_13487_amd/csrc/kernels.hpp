@@ -4,17 +4,21 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdint>
 
 namespace dgbgk {
 
 constexpr int kMaxP = 8;
 constexpr int kMaxN1 = kMaxP + 1;
 constexpr int kBlock = 256;  // threads per work-group of the stage kernel
+constexpr int kStreamDoubles = 16;  // f doubles per thread and block in the persistent kernel
+constexpr int kStreamMaxP = 3;      // higher orders hold too many nodal values per row
 
 // Everything one launch of the fused RK-stage kernel needs.  Passed by value:
 // the reference-element tables ride in the kernel-argument segment.
+// Device states are element-major, f[k][q][n] (element k, velocity q, node n).
 struct StageArgs {
-  const double *fs;    // stage input state f_s[q][k][n]
+  const double *fs;    // stage input state f_s[k][q][n]
   const double *fn;    // state at the start of the step f_n
   double *acc;         // RK4 accumulator
   double *out;         // stage output (f_{s+1}, f_{n+1}, or L(f_s) when stage 0)
@@ -51,6 +55,14 @@ size_t stage_lds_bytes(int p, int E, int Qt);
 hipError_t launch_stage(int p, const StageArgs &a, size_t lds_bytes, int ntiles,
                         hipStream_t stream);
 
+// The persistent pipelined stage kernel applies to fused blocks with at most
+// kBlock velocity rows (E * Q) and at most kStreamDoubles * kBlock f values,
+// p <= kStreamMaxP, and f arrays below 4 GiB (32-bit offsets).
+bool stream_applicable(int p, int E, int Q, int64_t K);
+size_t stream_lds_bytes(int p, int E, int Q);
+hipError_t launch_stream(int p, const StageArgs &a, size_t lds_bytes, int groups,
+                         hipStream_t stream);
+
 // rho, ux, uy of f at every node (any output may be null) and, when rhow is
 // non-null, the diffuse-wall densities of every wall face node.
 hipError_t launch_moments(const double *f, const double *vel, int K, int p, int Q, int nx,
@@ -66,6 +78,10 @@ hipError_t launch_residual(const double *k, const double *vel, int K, int Np, in
 hipError_t launch_init_equilibrium(double *f, const double *vel, int K, int Np, int Q,
                                    double rho0, double ux0, double uy0, double theta,
                                    hipStream_t stream);
+
+// f[q][k][n] -> f[k][q][n] (to_element_major = 1) or back (0).
+hipError_t launch_transpose(const double *src, double *dst, int K, int Np, int Q,
+                            int to_element_major, hipStream_t stream);
 
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v,
                            hipStream_t stream);

@@ -51,6 +51,8 @@ RHS_CASES = [
     ("cavity_2x2_p8_nc4", workloads.cavity(n=2, p=8, m=4), None),
     ("cavity_9x7_p3_nc9_oddQ", workloads.cavity(n=9, ny=7, p=3, m=9, lid=0.15), None),
     ("cavity_9x7_p3_nc9_tiled", workloads.cavity(n=9, ny=7, p=3, m=9, lid=0.15), (2, 10)),
+    ("cavity_9x7_p3_nc9_persistent", workloads.cavity(n=9, ny=7, p=3, m=9, lid=0.15), (4, 0)),
+    ("couette_8x8_p2_gh4_persistent", workloads.couette(nx=8, ny=8, p=2), (4, 0)),
     ("collisionless_4x4_p3", workloads.periodic_box(nx=4, ny=4, p=3, tau=float("inf")), None),
 ]
 
@@ -98,7 +100,7 @@ def test_couette_200_steps_matches_oracle(oracle_mod):
     assert g.steps_taken() == spec.steps
 
 
-@pytest.mark.parametrize("tiling", [None, (2, 13)])
+@pytest.mark.parametrize("tiling", [None, (2, 13), (4, 0)])
 def test_cavity_perturbed_steps_match_oracle(oracle_mod, tiling):
     _say(f"[gpu] cavity 10x7 p3 nc10 perturbed, tiling={tiling}")
     spec = workloads.cavity(n=10, ny=7, p=3, m=10, lid=0.1, kn=0.5)
@@ -125,6 +127,24 @@ def test_fused_and_tiled_agree():
         s.init_equilibrium()
         s.step(30, s.stable_dt(0.2))
     assert _rel(b.get_state(), a.get_state()) < 1e-13
+
+
+@pytest.mark.parametrize("n,ny,p,m", [(8, 8, 3, 16), (9, 7, 3, 9), (5, 3, 2, 4), (3, 5, 1, 8)])
+def test_persistent_and_per_block_kernels_identical(n, ny, p, m):
+    # the persistent kernel runs the same arithmetic in the same order as the
+    # one-block-per-work-group kernel, so the states agree bit for bit
+    _say(f"[gpu] persistent vs per-block {n}x{ny} p{p} nc{m}")
+    spec = workloads.cavity(n=n, ny=ny, p=p, m=m, lid=0.1)
+    a = binding.Solver.from_spec(spec)
+    b = binding.Solver.from_spec(spec)
+    a.set_tiling(4, 0)
+    assert a.tiling()["persistent"] and b.tiling()["fused"] and not b.tiling()["persistent"]
+    f = workloads.perturbed_state(5, a.w, a.K, a.Np, amp=0.05)
+    assert np.array_equal(a.rhs(f), b.rhs(f))
+    for s_ in (a, b):
+        s_.set_state(f)
+        s_.step(12, s_.stable_dt(0.2))
+    assert np.array_equal(a.get_state(), b.get_state())
 
 
 def test_residual_and_moments_parity(oracle_mod):
