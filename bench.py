@@ -8,8 +8,10 @@ fused stage kernels); the steady-state residual is evaluated on the device
 every 50 steps inside the timed region.
 
 Prints one JSON line with the metric, a roofline object for the stage kernel
-(its average duration measured with HIP events on the stream it runs on) and
-the CPU oracle timed on a bounded sample of the same workload.
+(its average duration measured with HIP events on the stream it runs on), the
+CPU oracle timed on a bounded sample of the same workload, and the precision
+path (FP32 storage) measured on the same GPU: on this workload and on the
+precision workload (cavity 128x128 quads, p=4, NC 24x24, Kn=8) beside FP64.
 """
 import argparse
 import hashlib
@@ -23,6 +25,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 ALG_BYTES_PER_DOF_STAGE = 32.0  # FP64 RK4, 3 registers: 24/40/40/24 B per stage -> 32 mean
+# FP32 increment-form RK4: 12/20/20/16 B per stage -> 17 mean
+ALG_BYTES_PER_DOF_STAGE_FP32 = 17.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_cavity64x64_p3_nc16_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2012_13487_amd", "csrc", "kernels.hip")
 
@@ -70,6 +74,54 @@ def cpu_baseline(spec, budget_s):
                       f"FP64 C oracle, OpenMP over elements"}
 
 
+def time_steps(solver, steps, dt):
+    """Wall time of `steps` RK4 steps on the solver's stream (HIP events)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    solver.step(steps, dt)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
+
+
+def precision_path(steps_small, steps_big):
+    """DOF-updates/s of the FP32-storage path next to FP64, on the benchmark
+    workload and on the precision workload (all inputs resident in HBM)."""
+    import workloads
+    from paper_2012_13487_amd import Solver
+    out = {}
+    for key, spec, steps, precs in (
+            ("cavity64x64_p3_nc16", workloads.CAVITY_64x64_P3_NC16, steps_small, ("fp32",)),
+            ("cavity128x128_p4_nc24_kn8", workloads.CAVITY_128x128_P4_NC24_KN8, steps_big,
+             ("fp32", "fp64"))):
+        entry = {}
+        for prec in precs:
+            g = Solver.from_spec(spec, precision=prec, stream="torch", torch_memory=True)
+            dt = g.stable_dt(spec.cfl)
+            g.init_equilibrium()
+            time_steps(g, 2, dt)
+            ms = time_steps(g, steps, dt)
+            stage_us = 1000.0 * ms / (4 * steps)
+            bpd = ALG_BYTES_PER_DOF_STAGE_FP32 if prec == "fp32" else ALG_BYTES_PER_DOF_STAGE
+            ach = bpd * g.ndof / (stage_us * 1e-6) / 1e9
+            entry["dof"] = g.ndof
+            entry[prec] = {"value": g.ndof * 4 * steps / (ms / 1000.0), "unit": "DOF-updates/s",
+                           "avg_launch_us": stage_us, "alg_bytes_per_dof_stage": bpd,
+                           "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS, "steps": steps,
+                           "tiling": g.tiling()}
+            g.close()
+        out[key] = entry
+    big = out["cavity128x128_p4_nc24_kn8"]
+    out["fp32_over_fp64_precision_workload"] = big["fp32"]["value"] / big["fp64"]["value"]
+    out["note"] = ("FP32 = state stored as the FP32 deviation from w_q; moments, wall densities and "
+                   "residual in FP64; error vs the FP64 oracle measured by the GPU tests (<= 1e-5)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +130,7 @@ def main():
     ap.add_argument("--resid-every", type=int, default=50)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-path", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB (5 times), to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters of the stage kernel")
@@ -176,6 +229,9 @@ def main():
         },
         "cpu_baseline": None,
     }
+    del g
+    if not args.no_precision_path:
+        out["precision_path"] = precision_path(100, 20)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -64,7 +64,20 @@ typedef enum {
 
 typedef enum { DGBGK_BC_PERIODIC = 0, DGBGK_BC_DIFFUSE_WALL = 1 } dgbgk_bc;
 
-typedef enum { DGBGK_FP64 = 0 } dgbgk_precision;
+/* Arithmetic of the time step.
+ *   DGBGK_FP64: every value FP64.
+ *   DGBGK_FP32: the state is stored and streamed in FP32 as the deviation
+ *     g = f - w_q rho_ref (rho_ref = 1) from the rest equilibrium; the
+ *     volume term, lifted jumps, collision and RK update run in FP32, the node
+ *     moments rho, rho u, the diffuse-wall densities of eq. (8) and the wall
+ *     exterior states are formed in FP64, and so is the residual.  Host
+ *     arrays stay FP64 f (converted on the device).
+ *   DGBGK_FP32_BF16MMA: as DGBGK_FP32, with the volume term's contractions
+ *     Dr g, Ds g on bf16 matrix cores with FP32 accumulation (DGBGK_ENOTSUP
+ *     where this build has no such kernel).
+ * The FP32 precisions run only the fused form (all velocities of an element
+ * in one work-group); create returns DGBGK_ENOTSUP when that does not fit. */
+typedef enum { DGBGK_FP64 = 0, DGBGK_FP32 = 1, DGBGK_FP32_BF16MMA = 2 } dgbgk_precision;
 
 /* Problem statement (Sec. II: mesh and polynomial order, velocity set and
  * weights, relaxation time, wall and lid conditions). */
@@ -158,7 +171,8 @@ int dgbgk_set_state(dgbgk_solver *s, const double *f, size_t count);
 int dgbgk_get_state(dgbgk_solver *s, double *f, size_t count);
 
 /* Device address of the current state, element-major f[k][q][n] (FP64,
- * Q*K*Np doubles), valid until the next dgbgk_step(); for zero-copy views. */
+ * Q*K*Np doubles; for the FP32 precisions the FP32 deviation g[k][q][n] =
+ * f - w_q), valid until the next dgbgk_step(); for zero-copy views. */
 int dgbgk_state_device_ptr(dgbgk_solver *s, void **ptr);
 
 /* Advance nsteps classical RK4 steps of size dt (enqueued; returns at once).

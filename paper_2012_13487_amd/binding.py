@@ -14,7 +14,8 @@ LIB_PATH = os.path.join(HERE, "libdgbgk.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 BC_PERIODIC, BC_DIFFUSE_WALL = 0, 1
-FP64 = 0
+FP64, FP32, FP32_BF16MMA = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_bf16mma": FP32_BF16MMA}
 
 _dp = C.POINTER(C.c_double)
 
@@ -156,21 +157,29 @@ def _problem(nx, ny, p, vel, tau, bc, wall_u, x0, y0, lx, ly):
     return pb
 
 
-def required_bytes(nx, ny, p, vel, tau, bc, wall_u, x0=0.0, y0=0.0, lx=1.0, ly=1.0):
+def required_bytes(nx, ny, p, vel, tau, bc, wall_u, x0=0.0, y0=0.0, lx=1.0, ly=1.0,
+                   precision=FP64):
     pb = _problem(nx, ny, p, vel, tau, bc, wall_u, x0, y0, lx, ly)
     n = C.c_size_t()
-    _check(lib().dgbgk_required_bytes(C.byref(pb), FP64, C.byref(n)))
+    _check(lib().dgbgk_required_bytes(C.byref(pb), _prec(precision), C.byref(n)))
     return n.value
 
 
+def _prec(precision):
+    return PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+
+
 class Solver:
-    """One DG-BGK problem on the GPU.  State layout f[q][k][n], FP64.
+    """One DG-BGK problem on the GPU.  Host state arrays f[q][k][n], FP64.
 
     ``stream``: a HIP stream handle (int) or "torch" for torch's current
-    stream; ``torch_memory``: take device memory from a torch tensor."""
+    stream; ``torch_memory``: take device memory from a torch tensor;
+    ``precision``: FP64, FP32 or FP32_BF16MMA (or "fp64", "fp32",
+    "fp32_bf16mma")."""
 
     def __init__(self, nx, ny, p, velset, tau, bc, wall_u, x0=0.0, y0=0.0, lx=1.0, ly=1.0,
-                 stream=None, torch_memory=False):
+                 stream=None, torch_memory=False, precision=FP64):
+        self.precision = _prec(precision)
         self._h = None
         self.vel = velocity_set(velset)
         self.ex, self.ey, self.w, self.theta = self.vel
@@ -182,7 +191,7 @@ class Solver:
             if stream == "torch":
                 stream = torch.cuda.current_stream().cuda_stream
         h = C.c_void_p()
-        _check(lib().dgbgk_create(C.byref(pb), FP64, C.c_void_p(stream or 0), C.byref(h)))
+        _check(lib().dgbgk_create(C.byref(pb), self.precision, C.c_void_p(stream or 0), C.byref(h)))
         self._h = h.value
         K, Np, Nfp, Q = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
         self._call("dgbgk_sizes", C.byref(K), C.byref(Np), C.byref(Nfp), C.byref(Q))
@@ -192,7 +201,7 @@ class Solver:
         if torch_memory:
             import torch
             nbytes = C.c_size_t()
-            _check(lib().dgbgk_required_bytes(C.byref(pb), FP64, C.byref(nbytes)))
+            _check(lib().dgbgk_required_bytes(C.byref(pb), self.precision, C.byref(nbytes)))
             self._buf = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
             self._call("dgbgk_bind_buffers", C.c_void_p(self._buf.data_ptr()), nbytes.value)
 

@@ -16,6 +16,7 @@
 #include "dgbgk.h"
 #include "host_math.hpp"
 #include "kernels.hpp"
+#include "kernels32.hpp"
 
 using namespace dgbgk;
 
@@ -29,17 +30,23 @@ constexpr int kMaxQ = 4096;
 size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t fn, acc, a, b, vel, feqb, wmom, mom, rhow, u64, total;
+  size_t fn, acc, a, b, xfer, vel, feqb, wmom, mom, rhow, u64, total;
 };
 
-Layout make_layout(int64_t K, int Np, int Nfp, int Q) {
+bool is_fp32(int precision) { return precision == DGBGK_FP32 || precision == DGBGK_FP32_BF16MMA; }
+
+// State registers (FP64, or the FP32 deviation), an FP64 transfer buffer for
+// the FP32 precisions, then the small tables.
+Layout make_layout(int64_t K, int Np, int Nfp, int Q, int precision) {
   Layout L{};
-  const size_t dof = (size_t)K * Np * Q * sizeof(double);
+  const size_t ndof = (size_t)K * Np * Q;
+  const size_t dof = ndof * (is_fp32(precision) ? sizeof(float) : sizeof(double));
   size_t off = 0;
   L.fn = off;   off += round_up(dof);
   L.acc = off;  off += round_up(dof);
   L.a = off;    off += round_up(dof);
   L.b = off;    off += round_up(dof);
+  L.xfer = off; off += is_fp32(precision) ? round_up(ndof * sizeof(double)) : 0;
   L.vel = off;  off += round_up((size_t)3 * Q * sizeof(double));
   L.feqb = off; off += round_up((size_t)4 * Q * sizeof(double));
   L.wmom = off; off += round_up((size_t)16 * Q * sizeof(double));
@@ -72,7 +79,12 @@ struct dgbgk_solver {
   void *base = nullptr;
   bool owns = false;
   Layout lay{};
-  double *d_fn = nullptr, *d_acc = nullptr, *d_a = nullptr, *d_b = nullptr;
+  double *d_fn = nullptr, *d_acc = nullptr, *d_a = nullptr, *d_b = nullptr;  // FP64 states
+  float *g_fn = nullptr, *g_acc = nullptr, *g_a = nullptr, *g_b = nullptr;   // FP32 deviations
+  double *d_xfer = nullptr;  // FP64 staging of host transfers (FP32 precisions)
+  int prec = DGBGK_FP64;
+  double rho_ref = 1.0;      // reference density of the FP32 deviation g = f - w rho_ref
+  double mconst[7] = {0, 0, 0, 0, 0, 0, 0};
   double *d_vel = nullptr, *d_feqb = nullptr, *d_wmom = nullptr, *d_mom = nullptr, *d_rhow = nullptr;
   unsigned long long *d_u64 = nullptr;
   // launch configuration
@@ -140,9 +152,33 @@ int validate(const dgbgk_problem *pb, dgbgk_solver *s) {
   return DGBGK_OK;
 }
 
+// FP32 precisions: always the fused form; E elements per work-group while
+// the tile stays within 64 KB of LDS (at least one element, up to 160 KB).
+void choose_tiling32(dgbgk_solver *s) {
+  const int NP = s->Np;
+  const bool bf = s->prec == DGBGK_FP32_BF16MMA;
+  int E = 1;
+  while ((int64_t)E * 2 * s->Q * NP <= 8192 && E * 2 <= s->K &&
+         stage32_lds_bytes(s->p, E * 2, s->Q, bf) <= kFusedLdsLimit)
+    E *= 2;
+  s->E = E;
+  s->log2E = 0;
+  while ((1 << s->log2E) < E) ++s->log2E;
+  s->fused = 1;
+  s->persistent = 0;
+  s->Qt = s->Q;
+  s->ntiles = 1;
+  s->nblk = (int)((s->K + E - 1) / E);
+  s->lds = stage32_lds_bytes(s->p, E, s->Q, bf);
+}
+
 // Launch configuration: fused (all velocities of E elements per work-group)
 // when its LDS fits, else velocity tiles with a separate moments pass.
 void choose_tiling(dgbgk_solver *s) {
+  if (is_fp32(s->prec)) {
+    choose_tiling32(s);
+    return;
+  }
   const int NP = s->Np;
   const int G = kBlock / NP;
   int E = 1;
@@ -208,6 +244,11 @@ int ensure_device(dgbgk_solver *s) {
   s->d_acc = (double *)(b + s->lay.acc);
   s->d_a = (double *)(b + s->lay.a);
   s->d_b = (double *)(b + s->lay.b);
+  s->g_fn = (float *)(b + s->lay.fn);
+  s->g_acc = (float *)(b + s->lay.acc);
+  s->g_a = (float *)(b + s->lay.a);
+  s->g_b = (float *)(b + s->lay.b);
+  s->d_xfer = is_fp32(s->prec) ? (double *)(b + s->lay.xfer) : nullptr;
   s->d_vel = (double *)(b + s->lay.vel);
   s->d_feqb = (double *)(b + s->lay.feqb);
   s->d_wmom = (double *)(b + s->lay.wmom);
@@ -286,10 +327,80 @@ StageArgs base_args(const dgbgk_solver *s) {
   return a;
 }
 
+Stage32Args base_args32(const dgbgk_solver *s) {
+  Stage32Args a;
+  std::memset(&a, 0, sizeof a);
+  const int N1 = s->p + 1;
+  for (int i = 0; i < N1 * N1; ++i) a.D1[i] = (float)s->D1[i];
+  for (int i = 0; i < N1; ++i) {
+    a.lift_lo[i] = (float)s->lift_lo[i];
+    a.lift_hi[i] = (float)s->lift_hi[i];
+  }
+  a.vel = s->d_vel;
+  a.feqb = s->d_feqb;
+  a.wmom = s->d_wmom;
+  a.rx = (float)(2.0 / s->hx);
+  a.sy = (float)(2.0 / s->hy);
+  a.fsx = (float)(2.0 / s->hx);
+  a.fsy = (float)(2.0 / s->hy);
+  a.theta_inv = (float)(1.0 / s->pb.theta);
+  a.half_theta2_inv = (float)(1.0 / (2.0 * s->pb.theta * s->pb.theta));
+  a.half_theta_inv = 1.0 / (2.0 * s->pb.theta);
+  a.inv_tau = std::isinf(s->pb.tau) ? 0.0f : (float)(1.0 / s->pb.tau);
+  for (int sd = 0; sd < 4; ++sd) a.wall_den_inv[sd] = s->wall_den_inv[sd];
+  for (int c = 0; c < 7; ++c) a.mconst[c] = s->mconst[c];
+  a.rho_ref = s->rho_ref;
+  a.nx = s->pb.nx;
+  a.ny = s->pb.ny;
+  a.K = (int)s->K;
+  a.Q = s->Q;
+  a.E = s->E;
+  a.nblk = s->nblk;
+  a.wall_mask = s->wall_mask;
+  a.periodic_x = s->pb.bc[1] == DGBGK_BC_PERIODIC;
+  a.periodic_y = s->pb.bc[0] == DGBGK_BC_PERIODIC;
+  return a;
+}
+
+void rk_coefficients(int stage, double dt, double &ca, double &co) {
+  ca = co = 0.0;
+  switch (stage) {
+    case 1: ca = dt / 6.0; co = dt / 2.0; break;
+    case 2: ca = dt / 3.0; co = dt / 2.0; break;
+    case 3: ca = dt / 3.0; co = dt; break;
+    case 4: ca = dt / 6.0; co = 0.0; break;
+    default: break;
+  }
+}
+
+// One FP32 stage on deviation arrays.
+int run_stage32(dgbgk_solver *s, int stage, const float *fs, float *out, double dt,
+                double *rhow_out) {
+  Stage32Args a = base_args32(s);
+  a.fs = fs;
+  a.fn = s->g_fn;
+  a.acc = s->g_acc;
+  a.out = out;
+  a.stage = stage;
+  a.rhow_out = rhow_out;
+  double ca, co;
+  rk_coefficients(stage, dt, ca, co);
+  a.c_acc = (float)ca;
+  a.c_out = (float)co;
+  hipError_t e = launch_stage32(s->p, a, s->lds, s->prec == DGBGK_FP32_BF16MMA, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "FP32 stage kernel");
+  return DGBGK_OK;
+}
+
 // One stage: L(fs) combined into the RK4 registers (stage 1..4) or written to
-// out (stage 0).  Tiled mode first reduces the moments of fs.
-int run_stage(dgbgk_solver *s, int stage, const double *fs, double *out, double dt,
+// out (stage 0).  Tiled mode first reduces the moments of fs.  The state
+// pointers are FP64 arrays, or FP32 deviation arrays for the FP32 precisions.
+int run_stage(dgbgk_solver *s, int stage, const void *fs_, void *out_, double dt,
               double *rhow_out = nullptr) {
+  if (is_fp32(s->prec))
+    return run_stage32(s, stage, (const float *)fs_, (float *)out_, dt, rhow_out);
+  const double *fs = (const double *)fs_;
+  double *out = (double *)out_;
   hipError_t e;
   if (!s->fused) {
     e = launch_moments(fs, s->d_vel, (int)s->K, s->p, s->Q, s->pb.nx, s->pb.ny, s->wall_mask,
@@ -304,13 +415,7 @@ int run_stage(dgbgk_solver *s, int stage, const double *fs, double *out, double 
   a.out = out;
   a.stage = stage;
   a.rhow_out = rhow_out;
-  switch (stage) {
-    case 1: a.c_acc = dt / 6.0; a.c_out = dt / 2.0; break;
-    case 2: a.c_acc = dt / 3.0; a.c_out = dt / 2.0; break;
-    case 3: a.c_acc = dt / 3.0; a.c_out = dt; break;
-    case 4: a.c_acc = dt / 6.0; a.c_out = 0.0; break;
-    default: break;
-  }
+  rk_coefficients(stage, dt, a.c_acc, a.c_out);
   if (s->persistent) {
     const int groups = (int)std::min<int64_t>(s->nblk, (int64_t)s->num_cu);
     e = launch_stream(s->p, a, s->lds, groups, s->stream);
@@ -325,7 +430,7 @@ int run_stage(dgbgk_solver *s, int stage, const double *fs, double *out, double 
 
 extern "C" {
 
-const char *dgbgk_version(void) { return "dgbgk 0.1 (gfx950, FP64)"; }
+const char *dgbgk_version(void) { return "dgbgk 0.2 (gfx950; FP64, FP32 storage)"; }
 
 const char *dgbgk_last_error(const dgbgk_solver *s) {
   if (!s) return g_create_error.c_str();
@@ -376,9 +481,10 @@ int dgbgk_required_bytes(const dgbgk_problem *pb, int32_t precision, size_t *byt
   if (!bytes) return fail(nullptr, DGBGK_EINVAL, "bytes is NULL");
   int rc = validate(pb, nullptr);
   if (rc) return rc;
-  if (precision != DGBGK_FP64) return fail(nullptr, DGBGK_ENOTSUP, "only DGBGK_FP64 is built");
+  if (precision != DGBGK_FP64 && !is_fp32(precision))
+    return fail(nullptr, DGBGK_EINVAL, "unknown precision %d", precision);
   const int N1 = pb->p + 1;
-  *bytes = make_layout((int64_t)pb->nx * pb->ny, N1 * N1, N1, pb->q).total;
+  *bytes = make_layout((int64_t)pb->nx * pb->ny, N1 * N1, N1, pb->q, precision).total;
   return DGBGK_OK;
 }
 
@@ -388,9 +494,15 @@ int dgbgk_create(const dgbgk_problem *pb, int32_t precision, void *hip_stream,
   *out = nullptr;
   int rc = validate(pb, nullptr);
   if (rc) return rc;
-  if (precision != DGBGK_FP64) return fail(nullptr, DGBGK_ENOTSUP, "only DGBGK_FP64 is built");
+  if (precision != DGBGK_FP64 && !is_fp32(precision))
+    return fail(nullptr, DGBGK_EINVAL, "unknown precision %d", precision);
+  if (precision == DGBGK_FP32_BF16MMA && !bf16_contraction_available(pb->p))
+    return fail(nullptr, DGBGK_ENOTSUP, "bf16 contractions are built for p <= 4");
+  if (is_fp32(precision) && (int64_t)pb->nx * pb->ny * pb->q * (pb->p + 1) * (pb->p + 1) >= ((int64_t)1 << 31))
+    return fail(nullptr, DGBGK_ENOTSUP, "FP32 path: more than 2^31 degrees of freedom");
   dgbgk_solver *s = new (std::nothrow) dgbgk_solver;
   if (!s) return fail(nullptr, DGBGK_ENOMEM, "out of host memory");
+  s->prec = precision;
   s->pb = *pb;
   s->Q = pb->q;
   s->ex.assign(pb->ex, pb->ex + pb->q);
@@ -446,8 +558,19 @@ int dgbgk_create(const dgbgk_problem *pb, int32_t precision, void *hip_stream,
   }
   const double uref = umax > 0.0 ? umax : 1.0;
   s->resid_scale = std::fmin(pb->lx, pb->ly) / uref;
-  s->lay = make_layout(s->K, s->Np, s->Nfp, s->Q);
+  // constant part of the moments of f = g + w rho_ref (FP32 precisions)
+  for (int q = 0; q < s->Q; ++q) {
+    const double cx = s->ex[q], cy = s->ey[q], wr = s->w[q] * s->rho_ref;
+    const double W[7] = {1.0, cx, cy, cy < 0.0 ? -cy : 0.0, cx > 0.0 ? cx : 0.0,
+                         cy > 0.0 ? cy : 0.0, cx < 0.0 ? -cx : 0.0};
+    for (int c = 0; c < 7; ++c) s->mconst[c] += W[c] * wr;
+  }
+  s->lay = make_layout(s->K, s->Np, s->Nfp, s->Q, precision);
   choose_tiling(s);
+  if (is_fp32(precision) && s->lds > 160 * 1024) {
+    delete s;
+    return fail(nullptr, DGBGK_ENOTSUP, "FP32 path: one element's velocities do not fit in LDS");
+  }
   *out = s;
   return DGBGK_OK;
 }
@@ -564,8 +687,12 @@ int dgbgk_init_equilibrium(dgbgk_solver *s, double rho0, double ux0, double uy0)
     return fail(s, DGBGK_EINVAL, "rho0 must be > 0 and u0 finite");
   int rc = ensure_device(s);
   if (rc) return rc;
-  hipError_t e = launch_init_equilibrium(s->d_fn, s->d_vel, (int)s->K, s->Np, s->Q, rho0, ux0, uy0,
-                                         s->pb.theta, s->stream);
+  hipError_t e =
+      is_fp32(s->prec)
+          ? launch_init_equilibrium32(s->g_fn, s->d_vel, (int)s->K, s->Np, s->Q, rho0, ux0, uy0,
+                                      s->pb.theta, s->rho_ref, s->stream)
+          : launch_init_equilibrium(s->d_fn, s->d_vel, (int)s->K, s->Np, s->Q, rho0, ux0, uy0,
+                                    s->pb.theta, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "init kernel");
   s->have_state = true;
   s->steps = 0;
@@ -578,9 +705,16 @@ int dgbgk_set_state(dgbgk_solver *s, const double *f, size_t count) {
   if (!f || count != need) return fail(s, DGBGK_EINVAL, "state needs %zu doubles", need);
   int rc = ensure_device(s);
   if (rc) return rc;
-  // host order f[q][k][n] into a stage buffer, then element-major into f_n
-  hipError_t e = hipMemcpyAsync(s->d_b, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
-  if (e == hipSuccess) e = launch_transpose(s->d_b, s->d_fn, (int)s->K, s->Np, s->Q, 1, s->stream);
+  // host order f[q][k][n] into a staging buffer, then element-major into f_n
+  hipError_t e;
+  if (is_fp32(s->prec)) {
+    e = hipMemcpyAsync(s->d_xfer, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+      e = launch_to_dev32(s->d_xfer, s->g_fn, s->d_vel, (int)s->K, s->Np, s->Q, s->rho_ref, s->stream);
+  } else {
+    e = hipMemcpyAsync(s->d_b, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = launch_transpose(s->d_b, s->d_fn, (int)s->K, s->Np, s->Q, 1, s->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "set_state copy");
   s->have_state = true;
@@ -593,9 +727,13 @@ int dgbgk_get_state(dgbgk_solver *s, double *f, size_t count) {
   const size_t need = (size_t)s->K * s->Np * s->Q;
   if (!f || count != need) return fail(s, DGBGK_EINVAL, "state needs %zu doubles", need);
   if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
-  hipError_t e = launch_transpose(s->d_fn, s->d_b, (int)s->K, s->Np, s->Q, 0, s->stream);
+  double *stage = is_fp32(s->prec) ? s->d_xfer : s->d_b;
+  hipError_t e = is_fp32(s->prec)
+                     ? launch_from_dev32(s->g_fn, stage, s->d_vel, (int)s->K, s->Np, s->Q, s->rho_ref,
+                                         s->stream)
+                     : launch_transpose(s->d_fn, stage, (int)s->K, s->Np, s->Q, 0, s->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(f, s->d_b, need * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    e = hipMemcpyAsync(f, stage, need * sizeof(double), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "get_state copy");
   return DGBGK_OK;
@@ -606,7 +744,7 @@ int dgbgk_state_device_ptr(dgbgk_solver *s, void **ptr) {
   if (!ptr) return fail(s, DGBGK_EINVAL, "ptr is NULL");
   int rc = ensure_device(s);
   if (rc) return rc;
-  *ptr = s->d_fn;
+  *ptr = is_fp32(s->prec) ? (void *)s->g_fn : (void *)s->d_fn;
   return DGBGK_OK;
 }
 
@@ -619,10 +757,11 @@ int dgbgk_step(dgbgk_solver *s, int64_t nsteps, double dt) {
   for (int64_t it = 0; it < nsteps; ++it) {
     // registers: f_n, acc, and two stage buffers A/B so that a stage never
     // overwrites the state its neighbours still read.
-    if ((rc = run_stage(s, 1, s->d_fn, s->d_a, dt))) return rc;
-    if ((rc = run_stage(s, 2, s->d_a, s->d_b, dt))) return rc;
-    if ((rc = run_stage(s, 3, s->d_b, s->d_a, dt))) return rc;
-    if ((rc = run_stage(s, 4, s->d_a, s->d_fn, dt))) return rc;
+    void *fn = s->d_fn, *A = s->d_a, *B = s->d_b;
+    if ((rc = run_stage(s, 1, fn, A, dt))) return rc;
+    if ((rc = run_stage(s, 2, A, B, dt))) return rc;
+    if ((rc = run_stage(s, 3, B, A, dt))) return rc;
+    if ((rc = run_stage(s, 4, A, fn, dt))) return rc;
     ++s->steps;
   }
   return DGBGK_OK;
@@ -634,13 +773,25 @@ int dgbgk_rhs(dgbgk_solver *s, const double *f, double *k, size_t count) {
   if (!f || !k || count != need) return fail(s, DGBGK_EINVAL, "arrays need %zu doubles", need);
   int rc = ensure_device(s);
   if (rc) return rc;
-  hipError_t e = hipMemcpyAsync(s->d_b, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
-  if (e == hipSuccess) e = launch_transpose(s->d_b, s->d_a, (int)s->K, s->Np, s->Q, 1, s->stream);
-  if (e != hipSuccess) return hip_fail(s, e, "rhs input copy");
-  if ((rc = run_stage(s, 0, s->d_a, s->d_b, 0.0))) return rc;
-  e = launch_transpose(s->d_b, s->d_a, (int)s->K, s->Np, s->Q, 0, s->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(k, s->d_a, need * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  hipError_t e;
+  if (is_fp32(s->prec)) {
+    e = hipMemcpyAsync(s->d_xfer, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+      e = launch_to_dev32(s->d_xfer, s->g_a, s->d_vel, (int)s->K, s->Np, s->Q, s->rho_ref, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "rhs input copy");
+    if ((rc = run_stage(s, 0, s->g_a, s->g_b, 0.0))) return rc;
+    e = launch_from_dev32(s->g_b, s->d_xfer, s->d_vel, (int)s->K, s->Np, s->Q, 0.0, s->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(k, s->d_xfer, need * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  } else {
+    e = hipMemcpyAsync(s->d_b, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = launch_transpose(s->d_b, s->d_a, (int)s->K, s->Np, s->Q, 1, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "rhs input copy");
+    if ((rc = run_stage(s, 0, s->d_a, s->d_b, 0.0))) return rc;
+    e = launch_transpose(s->d_b, s->d_a, (int)s->K, s->Np, s->Q, 0, s->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(k, s->d_a, need * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "rhs output copy");
   return DGBGK_OK;
@@ -653,12 +804,19 @@ int dgbgk_wall_density(dgbgk_solver *s, const double *f, double *out, size_t cou
   if (!f || !out || count != need) return fail(s, DGBGK_EINVAL, "state needs %zu doubles", need);
   int rc = ensure_device(s);
   if (rc) return rc;
-  hipError_t e = hipMemcpyAsync(s->d_b, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
-  if (e == hipSuccess) e = launch_transpose(s->d_b, s->d_a, (int)s->K, s->Np, s->Q, 1, s->stream);
+  const bool f32 = is_fp32(s->prec);
+  hipError_t e = hipMemcpyAsync(f32 ? s->d_xfer : s->d_b, f, need * sizeof(double),
+                                hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess)
+    e = f32 ? launch_to_dev32(s->d_xfer, s->g_a, s->d_vel, (int)s->K, s->Np, s->Q, s->rho_ref,
+                              s->stream)
+            : launch_transpose(s->d_b, s->d_a, (int)s->K, s->Np, s->Q, 1, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "wall_density input copy");
   e = launch_fill_u64((unsigned long long *)s->d_rhow, nout, 0ull, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "fill kernel");
-  if ((rc = run_stage(s, 0, s->d_a, s->d_b, 0.0, s->fused ? s->d_rhow : nullptr))) return rc;
+  if ((rc = run_stage(s, 0, f32 ? (void *)s->g_a : (void *)s->d_a, f32 ? (void *)s->g_b : (void *)s->d_b,
+                      0.0, s->fused ? s->d_rhow : nullptr)))
+    return rc;
   e = hipMemcpyAsync(out, s->d_rhow, nout * sizeof(double), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "wall_density output copy");
@@ -670,8 +828,11 @@ static int residual_enqueue(dgbgk_solver *s) {
   if (rc) return rc;
   hipError_t e = launch_fill_u64(s->d_u64, 1, 0ull, s->stream);
   if (e == hipSuccess)
-    e = launch_residual(s->d_b, s->d_vel, (int)s->K, s->Np, s->Q, s->resid_scale, s->d_u64,
-                        s->stream);
+    e = is_fp32(s->prec)
+            ? launch_residual32(s->g_b, s->d_vel, (int)s->K, s->Np, s->Q, s->resid_scale, s->d_u64,
+                                s->stream)
+            : launch_residual(s->d_b, s->d_vel, (int)s->K, s->Np, s->Q, s->resid_scale, s->d_u64,
+                              s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "residual kernel");
   return DGBGK_OK;
 }
@@ -712,9 +873,13 @@ int dgbgk_moments(dgbgk_solver *s, double *rho, double *ux, double *uy) {
   if (!rho || !ux || !uy) return fail(s, DGBGK_EINVAL, "NULL output");
   if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
   const size_t KN = (size_t)s->K * s->Np;
-  hipError_t e = launch_moments(s->d_fn, s->d_vel, (int)s->K, s->p, s->Q, s->pb.nx, s->pb.ny, 0,
-                                s->wall_den_inv, s->d_mom, s->d_mom + KN, s->d_mom + 2 * KN, nullptr,
-                                s->stream);
+  hipError_t e =
+      is_fp32(s->prec)
+          ? launch_moments32(s->g_fn, s->d_vel, (int)s->K, s->Np, s->Q, s->rho_ref, s->d_mom,
+                             s->d_mom + KN, s->d_mom + 2 * KN, s->stream)
+          : launch_moments(s->d_fn, s->d_vel, (int)s->K, s->p, s->Q, s->pb.nx, s->pb.ny, 0,
+                           s->wall_den_inv, s->d_mom, s->d_mom + KN, s->d_mom + 2 * KN, nullptr,
+                           s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(rho, s->d_mom, KN * sizeof(double), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(ux, s->d_mom + KN, KN * sizeof(double), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(uy, s->d_mom + 2 * KN, KN * sizeof(double), hipMemcpyDeviceToHost, s->stream);
@@ -744,6 +909,8 @@ int dgbgk_steps_taken(const dgbgk_solver *s, int64_t *steps) {
 int dgbgk_set_tiling(dgbgk_solver *s, int32_t mode, int32_t velocities_per_tile) {
   if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
   if (mode < 0 || mode > 4) return fail(s, DGBGK_EINVAL, "mode must be 0..4");
+  if (is_fp32(s->prec) && (mode == 2 || mode == 4))
+    return fail(s, DGBGK_ENOTSUP, "the FP32 precisions run the fused per-block form only");
   if (velocities_per_tile < 0) return fail(s, DGBGK_EINVAL, "velocities_per_tile must be >= 0");
   const int saved_mode = s->tiling_mode, saved_qt = s->tiling_qt;
   s->tiling_mode = mode;

@@ -1,0 +1,560 @@
+// FP32-storage precision path of the RK stage (gfx950).
+//
+// The state is stored as the deviation g = f - w_q rho_ref in FP32,
+// element-major g[k][q][n].  Since w_q rho_ref is constant in space and time,
+// the RK update, the volume term (D1 annihilates constants) and the jumps
+// between neighbours are the same on g as on f; FP32 rounding is then relative
+// to the deviation rather than to f ~ w_q.  Following the method's split of
+// work, the node moments rho, rho u (Sec. II.A) and the diffuse-wall densities
+// of eq. (8) are reduced in FP64 (on the FP64 matrix cores, from the FP32
+// values converted exactly), and the wall exterior states
+// rho_w f^eq(1, u_b) - w rho_ref are formed in FP64; the volume term, the
+// lifted upwind jumps, the BGK collision with the second-order equilibrium of
+// eq. (5) and the RK4 update (classical RK4 in increment form, see rk32) run
+// in FP32.
+//
+// One work-group owns E elements and all Q velocities (the fused form of the
+// FP64 kernel): the block's tile is one contiguous run of E Q Np floats,
+// streamed with 16-byte accesses.
+#include "kernels32.hpp"
+
+#include <cmath>
+#include <type_traits>
+
+namespace dgbgk {
+
+namespace {
+
+typedef double double4v __attribute__((ext_vector_type(4)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBlock32 = 256;
+
+template <int P>
+struct Shape32 {
+  static constexpr int N1 = P + 1;
+  static constexpr int NP = N1 * N1;
+  static constexpr int NFP = N1;
+  static constexpr int S = NP | 1;  // odd LDS row stride: row-per-thread reads without conflicts
+  static constexpr int NB = (NP + 15) / 16;
+};
+
+// LDS layout in doubles: float tile, FP64 partial products, FP32 node
+// moments (8 per node), FP64 wall densities, neighbour table, and (bf16
+// variant) the contraction outputs of one 16-velocity group per wavefront.
+struct Lds32 {
+  int part, mom, rw, nbr, vol, total;
+};
+
+__host__ __device__ inline Lds32 lds32_layout(int NP, int NFP, int S, int E, int Q, bool bf16) {
+  Lds32 L;
+  const int tile_d = (E * Q * S + 1) / 2;
+  const int tasks = E * ((NP + 15) / 16);
+  const int pairs = tasks >= 4 ? tasks : 4;
+  L.part = (tile_d + 3) / 4 * 4;
+  L.mom = L.part + pairs * 7 * 16;      // float [E*NP][8] = 4 doubles per node
+  L.rw = L.mom + E * NP * 4;
+  L.nbr = L.rw + E * 4 * NFP;
+  L.vol = (L.nbr + (E * 4 + 1) / 2 + 3) / 4 * 4;
+  // bf16: per wavefront a [2 NP][16] float block (Dr g and Ds g of 16 velocities)
+  L.total = L.vol + (bf16 ? 4 * (2 * NP * 16) / 2 : 0);
+  return L;
+}
+
+__device__ inline int xcd_block32(int b, int nblk) {
+  const int per = nblk >> 3, rem = nblk & 7, x = b & 7;
+  return x * per + (x < rem ? x : rem) + (b >> 3);
+}
+
+__device__ inline int neighbour32(int k, int face, const Stage32Args &a) {
+  const int ex = k % a.nx, ey = k / a.nx;
+  switch (face) {
+    case 0: return ey > 0 ? k - a.nx : (a.periodic_y ? k + a.nx * (a.ny - 1) : -1);
+    case 1: return ex < a.nx - 1 ? k + 1 : (a.periodic_x ? k - (a.nx - 1) : -1);
+    case 2: return ey < a.ny - 1 ? k + a.nx : (a.periodic_y ? k - a.nx * (a.ny - 1) : -1);
+    default: return ex > 0 ? k - 1 : (a.periodic_x ? k + (a.nx - 1) : -1);
+  }
+}
+
+// Classical RK4 in increment form: acc holds d = sum_i b_i dt k_i (small, so
+// its FP32 rounding is relative to the increment, not to the state), and the
+// state is rounded once per step, g_{n+1} = g_n + (d + dt/6 k_4).
+//   MODE 1: d = dt/6 k,     out = g_n + dt/2 k      (x = g_n = g_s)
+//   MODE 2: d += dt/3 k,    out = g_n + c dt k      (x = g_n, y = d)
+//   MODE 4: out = g_n + (d + dt/6 k)                (x = g_n, y = d)
+//   MODE 0: out = k
+template <int MODE>
+__device__ __forceinline__ float rk32(float kv, float x, float y, float ca, float co, float &an) {
+  if (MODE == 0) return kv;
+  if (MODE == 1) { an = ca * kv; return x + co * kv; }
+  if (MODE == 2) { an = y + ca * kv; return x + co * kv; }
+  return x + (y + ca * kv);
+}
+
+// Round-to-nearest-even FP32 -> bf16 bits.
+__device__ __forceinline__ uint16_t bf16_bits(float v) {
+  uint32_t u = __float_as_uint(v);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// MODE: 0 writes L(f_s); 1 first RK4 stage; 2 second and third; 4 fourth.
+// CW: floats per global access (4 when Q Np is a multiple of 4, else 1).
+// BF: the volume term's contractions Dr g, Ds g on bf16 matrix cores.
+template <int P, int MODE, int CW, bool BF>
+__global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) {
+  using Sh = Shape32<P>;
+  constexpr int N1 = Sh::N1, NP = Sh::NP, NFP = Sh::NFP, S = Sh::S, NB = Sh::NB;
+  constexpr int U = 8;  // global accesses in flight per thread
+  using V = typename std::conditional<CW == 4, float4v, float>::type;
+  extern __shared__ double lds[];
+  const int E = a.E, Q = a.Q;
+  const Lds32 L = lds32_layout(NP, NFP, S, E, Q, BF);
+  float *tile = (float *)lds;
+  double *part = lds + L.part;
+  float *mom = (float *)(lds + L.mom);
+  double *rw = lds + L.rw;
+  int *nbr = (int *)(lds + L.nbr);
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int blk = xcd_block32(blockIdx.x, a.nblk);
+  const int k0 = blk * E;
+  const int Eb = min(E, a.K - k0);
+  const int QNP = Q * NP;
+  const int nflt = Eb * QNP;  // floats of this block (contiguous)
+  const int nch = nflt / CW;
+  const size_t boff = (size_t)k0 * QNP;
+
+  // ---- 0. neighbours (-1: wall) ------------------------------------------------
+  if (tid < E * 4) {
+    const int e = tid >> 2, fc = tid & 3;
+    nbr[tid] = e < Eb ? neighbour32(k0 + e, fc, a) : -1;
+  }
+
+  // ---- 1. the block's tile into LDS: row r = e Q + q, node n at r S + n --------
+  for (int c0 = tid; c0 < nch; c0 += nthr * U) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * nthr;
+      if (c < nch) v[u] = *reinterpret_cast<const V *>(a.fs + boff + (size_t)c * CW);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * nthr;
+      if (c >= nch) continue;
+#pragma unroll
+      for (int i = 0; i < CW; ++i) {
+        const int j = c * CW + i, r = j / NP, n = j - r * NP;
+        float x;
+        if constexpr (CW == 4) x = v[u][i];
+        else x = v[u];
+        tile[r * S + n] = x;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- 2. FP64 moments and wall densities (matrix cores) -----------------------
+  {
+    const int wave = tid >> 6, lane = tid & 63;
+    const int tasks = E * NB;
+    const int ks = tasks >= 4 ? 1 : 4 / tasks;
+    const int qper = ((Q + ks - 1) / ks + 3) / 4 * 4;
+    for (int pr = wave; pr < tasks * ks; pr += nthr >> 6) {
+      const int t = pr / ks, sl = pr % ks;
+      const int e = t / NB, nb = t % NB;
+      const int node = nb * 16 + (lane & 15);
+      const int qa = sl * qper, qe = min(Q, qa + qper);
+      double4v acc = {0.0, 0.0, 0.0, 0.0}, acc1 = acc, acc2 = acc, acc3 = acc;
+      if (e < Eb) {
+        constexpr int KB = 8;
+        for (int qb = qa; qb < qe; qb += 4 * KB) {
+          double av[KB], bv[KB];
+#pragma unroll
+          for (int t2 = 0; t2 < KB; ++t2) {
+            const int q = qb + 4 * t2 + (lane >> 4);
+            const bool in = q < qe;
+            av[t2] = in ? a.wmom[(size_t)q * 16 + (lane & 15)] : 0.0;
+            bv[t2] = (in && node < NP) ? (double)tile[(e * Q + q) * S + node] : 0.0;
+          }
+#pragma unroll
+          for (int t2 = 0; t2 < KB; t2 += 4) {
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t2], bv[t2], acc, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t2 + 1], bv[t2 + 1], acc1, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t2 + 2], bv[t2 + 2], acc2, 0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t2 + 3], bv[t2 + 3], acc3, 0, 0, 0);
+          }
+        }
+      }
+      acc += acc1 + acc2 + acc3;
+      // register v of a lane holds C[4 v + lane / 16][lane % 16]
+      if (node < NP) {
+        double *pp = part + ((size_t)pr * 7) * 16;
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const int row = 4 * v + (lane >> 4);
+          if (row < 7) pp[row * 16 + (lane & 15)] = acc[v];
+        }
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < E * NP; idx += nthr) {
+      const int e2 = idx / NP, n2 = idx % NP;
+      if (e2 < Eb) {
+        const int t = e2 * NB + n2 / 16, col = n2 % 16;
+        double sm[7];
+#pragma unroll
+        for (int c = 0; c < 7; ++c) sm[c] = 0.0;
+        for (int sl = 0; sl < ks; ++sl) {
+          const double *pp = part + ((size_t)(t * ks + sl) * 7) * 16;
+#pragma unroll
+          for (int c = 0; c < 7; ++c) sm[c] += pp[c * 16 + col];
+        }
+#pragma unroll
+        for (int c = 0; c < 7; ++c) sm[c] += a.mconst[c];
+        const double rho = sm[0], ux = sm[1] / rho, uy = sm[2] / rho;
+        float *m = mom + (e2 * NP + n2) * 8;
+        m[0] = (float)ux;
+        m[1] = (float)uy;
+        m[2] = (float)rho;
+        m[3] = (float)(rho - a.rho_ref);
+        m[4] = (float)((ux * ux + uy * uy) * a.half_theta_inv);
+        if (a.wall_mask != 0) {
+          const int i2 = n2 % N1, j2 = n2 / N1;
+          const bool on[4] = {nbr[e2 * 4 + 0] < 0 && j2 == 0, nbr[e2 * 4 + 1] < 0 && i2 == P,
+                              nbr[e2 * 4 + 2] < 0 && j2 == P, nbr[e2 * 4 + 3] < 0 && i2 == 0};
+          const int fm[4] = {i2, j2, i2, j2};
+#pragma unroll
+          for (int fc = 0; fc < 4; ++fc)
+            if (on[fc]) {
+              const double v = sm[3 + fc] * a.wall_den_inv[fc];
+              rw[(e2 * 4 + fc) * NFP + fm[fc]] = v;
+              if (a.rhow_out) a.rhow_out[((size_t)(k0 + e2) * 4 + fc) * NFP + fm[fc]] = v;
+            }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- 3. per velocity row: L(f) in FP32 ------------------------------------------
+  const int rows = E * Q;
+  for (int r0 = 0; r0 < rows; r0 += nthr) {
+    const int r = r0 + tid;
+    if (r >= rows) continue;
+    const int e = r / Q, q = r - e * Q;
+    if (e >= Eb) continue;
+    const float cx = (float)a.vel[q], cy = (float)a.vel[Q + q], wq = (float)a.vel[2 * Q + q];
+    const int fxc = cx > 0.0f ? 3 : 1, fyc = cy > 0.0f ? 0 : 2;  // inflow faces
+    const int nbx = nbr[e * 4 + fxc], nby = nbr[e * 4 + fyc];
+    // exterior traces of the two inflow faces
+    float px[NFP], py[NFP];
+    {
+      const bool gx = cx != 0.0f && nbx >= 0, gy = cy != 0.0f && nby >= 0;
+      const float *sx = a.fs + ((size_t)(nbx >= 0 ? nbx : 0) * Q + q) * NP + (cx > 0.0f ? P : 0);
+      const float *sy = a.fs + ((size_t)(nby >= 0 ? nby : 0) * Q + q) * NP + (cy > 0.0f ? N1 * P : 0);
+#pragma unroll
+      for (int m = 0; m < NFP; ++m) {
+        px[m] = gx ? sx[N1 * m] : 0.0f;
+        py[m] = gy ? sy[m] : 0.0f;
+      }
+    }
+    float f[NP];
+    const float *row = tile + r * S;
+#pragma unroll
+    for (int c = 0; c < NP; ++c) f[c] = row[c];
+    float kk[NP];
+    const float ax = cx * a.rx, ay = cy * a.sy;
+#pragma unroll
+    for (int j = 0; j < N1; ++j)
+#pragma unroll
+      for (int i = 0; i < N1; ++i) {
+        float dr = 0.0f, ds = 0.0f;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+          dr += a.D1[i * N1 + m] * f[m + N1 * j];
+          ds += a.D1[j * N1 + m] * f[i + N1 * m];
+        }
+        kk[i + N1 * j] = -(ax * dr + ay * ds);
+      }
+    // wall exterior state in deviation form, rho_w f^eq_q(1, u_b) - w_q rho_ref (FP64)
+    const double wrr = a.vel[2 * Q + q] * a.rho_ref;
+    if (cx != 0.0f) {
+      const float wx = a.fsx * (-fabsf(cx));
+      const double gb = a.feqb[fxc * Q + q];
+      const double *rwx = rw + (e * 4 + fxc) * NFP;
+#pragma unroll
+      for (int jj = 0; jj < N1; ++jj) {
+        const float own = cx > 0.0f ? f[N1 * jj] : f[N1 * jj + P];
+        const float ext = nbx >= 0 ? px[jj] : (float)(rwx[jj] * gb - wrr);
+        const float J = wx * (own - ext);
+#pragma unroll
+        for (int ii = 0; ii < N1; ++ii) kk[ii + N1 * jj] += (cx > 0.0f ? a.lift_lo[ii] : a.lift_hi[ii]) * J;
+      }
+    }
+    if (cy != 0.0f) {
+      const float wy = a.fsy * (-fabsf(cy));
+      const double gb = a.feqb[fyc * Q + q];
+      const double *rwy = rw + (e * 4 + fyc) * NFP;
+#pragma unroll
+      for (int ii = 0; ii < N1; ++ii) {
+        const float own = cy > 0.0f ? f[ii] : f[ii + N1 * P];
+        const float ext = nby >= 0 ? py[ii] : (float)(rwy[ii] * gb - wrr);
+        const float J = wy * (own - ext);
+#pragma unroll
+        for (int jj = 0; jj < N1; ++jj) kk[ii + N1 * jj] += (cy > 0.0f ? a.lift_lo[jj] : a.lift_hi[jj]) * J;
+      }
+    }
+    // collision: f^eq - f = w [(rho - rho_ref) + rho (e.u/theta + (e.u)^2/(2 theta^2)
+    //                          - |u|^2/(2 theta))] - g
+    const float *mm = mom + e * NP * 8;
+#pragma unroll
+    for (int nn = 0; nn < NP; ++nn) {
+      const float4v m4 = *reinterpret_cast<const float4v *>(mm + 8 * nn);
+      const float usq = mm[8 * nn + 4];
+      const float eu = cx * m4[0] + cy * m4[1];
+      const float dev = wq * (m4[3] + m4[2] * (eu * (a.theta_inv + eu * a.half_theta2_inv) - usq));
+      kk[nn] += (dev - f[nn]) * a.inv_tau;
+    }
+    float *roww = tile + r * S;
+#pragma unroll
+    for (int c = 0; c < NP; ++c) roww[c] = kk[c];
+  }
+  __syncthreads();
+
+  // ---- 4. RK4 update, coalesced over the contiguous block -----------------------
+  const float cacc = a.c_acc, cout = a.c_out;
+  const float *xr = (MODE == 1 ? a.fs : a.fn) + boff;
+  float *accr = a.acc + boff;
+  float *outr = a.out + boff;
+  for (int c0 = tid; c0 < nch; c0 += nthr * U) {
+    V x[U], y[U];
+    if (MODE != 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * nthr;
+        if (c < nch) x[u] = *reinterpret_cast<const V *>(xr + (size_t)c * CW);
+      }
+    }
+    if (MODE == 2 || MODE == 4) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * nthr;
+        if (c < nch) y[u] = *reinterpret_cast<const V *>(accr + (size_t)c * CW);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * nthr;
+      if (c >= nch) continue;
+      V o, an;
+#pragma unroll
+      for (int i = 0; i < CW; ++i) {
+        const int j = c * CW + i, r = j / NP, n = j - r * NP;
+        const float kv = tile[r * S + n];
+        float xi = 0.0f, yi = 0.0f, ai = 0.0f, oi;
+        if constexpr (CW == 4) {
+          if (MODE != 0) xi = x[u][i];
+          if (MODE == 2 || MODE == 4) yi = y[u][i];
+        } else {
+          if (MODE != 0) xi = x[u];
+          if (MODE == 2 || MODE == 4) yi = y[u];
+        }
+        oi = rk32<MODE>(kv, xi, yi, cacc, cout, ai);
+        if constexpr (CW == 4) {
+          o[i] = oi;
+          an[i] = ai;
+        } else {
+          o = oi;
+          an = ai;
+        }
+      }
+      *reinterpret_cast<V *>(outr + (size_t)c * CW) = o;
+      if (MODE == 1 || MODE == 2) *reinterpret_cast<V *>(accr + (size_t)c * CW) = an;
+    }
+  }
+}
+
+__global__ void to_dev32_kernel(const double *src, float *dst, const double *vel, size_t KNP, int Np,
+                                int Q, double offset) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // k * Np + n
+  const int q = blockIdx.y;
+  if (i >= KNP) return;
+  const double w = vel[2 * Q + q];
+  dst[((i / Np) * Q + q) * Np + i % Np] = (float)(src[(size_t)q * KNP + i] - offset * w);
+}
+
+__global__ void from_dev32_kernel(const float *src, double *dst, const double *vel, size_t KNP,
+                                  int Np, int Q, double offset) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i >= KNP) return;
+  const double w = vel[2 * Q + q];
+  dst[(size_t)q * KNP + i] = (double)src[((i / Np) * Q + q) * Np + i % Np] + offset * w;
+}
+
+__global__ void init_equilibrium32_kernel(float *g, const double *vel, size_t KNP, int Np, int Q,
+                                          double rho0, double ux0, double uy0, double theta,
+                                          double rho_ref) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i >= KNP) return;
+  const double cx = vel[q], cy = vel[Q + q], w = vel[2 * Q + q];
+  const double eu = cx * ux0 + cy * uy0, usq = ux0 * ux0 + uy0 * uy0;
+  const double feq = w * rho0 * (1.0 + eu / theta + eu * eu / (2.0 * theta * theta) - usq / (2.0 * theta));
+  g[((i / Np) * Q + q) * Np + i % Np] = (float)(feq - w * rho_ref);
+}
+
+__global__ __launch_bounds__(256) void moments32_kernel(const float *g, const double *vel, size_t KNP,
+                                                        int Np, int Q, double rho_ref, double *rho,
+                                                        double *ux, double *uy) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= KNP) return;
+  const size_t k = i / Np, n = i % Np;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int q = 0; q < Q; ++q) {
+    const double cx = vel[q], cy = vel[Q + q], w = vel[2 * Q + q];
+    const double v = (double)g[(k * Q + q) * Np + n] + w * rho_ref;
+    s0 += v;
+    s1 += cx * v;
+    s2 += cy * v;
+  }
+  if (rho) rho[i] = s0;
+  if (ux) ux[i] = s1 / s0;
+  if (uy) uy[i] = s2 / s0;
+}
+
+__device__ inline double nan_max32(double a, double b) { return (b > a || b != b) ? b : a; }
+
+__global__ __launch_bounds__(256) void residual32_kernel(const float *k, const double *vel, size_t KNP,
+                                                         int Np, int Q, double scale,
+                                                         unsigned long long *result) {
+  __shared__ double red[4];
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double m = 0.0;
+  if (i < KNP) {
+    const size_t kk = i / Np, n = i % Np;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int q = 0; q < Q; ++q) {
+      const double v = (double)k[(kk * Q + q) * Np + n];
+      s0 += v;
+      s1 += vel[q] * v;
+      s2 += vel[Q + q] * v;
+    }
+    m = nan_max32(nan_max32(fabs(s0), fabs(s1)), fabs(s2)) * scale;
+  }
+  for (int off = 32; off > 0; off >>= 1) m = nan_max32(m, __shfl_xor(m, off));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = nan_max32(b, red[w]);
+    atomicMax(result, (unsigned long long)__double_as_longlong(fabs(b)));
+  }
+}
+
+template <int P, int MODE, int CW, bool BF>
+hipError_t launch32_pmcb(const Stage32Args &a, size_t lds, hipStream_t st) {
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void *)stage32_kernel<P, MODE, CW, BF>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((stage32_kernel<P, MODE, CW, BF>), dim3((unsigned)a.nblk), dim3(kBlock32), lds,
+                     st, a);
+  return hipGetLastError();
+}
+
+template <int P, int MODE, bool BF>
+hipError_t launch32_pmb(const Stage32Args &a, size_t lds, hipStream_t st) {
+  if ((a.Q * (P + 1) * (P + 1)) % 4 == 0) return launch32_pmcb<P, MODE, 4, BF>(a, lds, st);
+  return launch32_pmcb<P, MODE, 1, BF>(a, lds, st);
+}
+
+template <int P, bool BF>
+hipError_t launch32_pb(const Stage32Args &a, size_t lds, hipStream_t st) {
+  switch (a.stage) {
+    case 0: return launch32_pmb<P, 0, BF>(a, lds, st);
+    case 1: return launch32_pmb<P, 1, BF>(a, lds, st);
+    case 2:
+    case 3: return launch32_pmb<P, 2, BF>(a, lds, st);
+    case 4: return launch32_pmb<P, 4, BF>(a, lds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <bool BF>
+hipError_t launch32_b(int p, const Stage32Args &a, size_t lds, hipStream_t st) {
+  switch (p) {
+    case 1: return launch32_pb<1, BF>(a, lds, st);
+    case 2: return launch32_pb<2, BF>(a, lds, st);
+    case 3: return launch32_pb<3, BF>(a, lds, st);
+    case 4: return launch32_pb<4, BF>(a, lds, st);
+    case 5: return launch32_pb<5, BF>(a, lds, st);
+    case 6: return launch32_pb<6, BF>(a, lds, st);
+    case 7: return launch32_pb<7, BF>(a, lds, st);
+    case 8: return launch32_pb<8, BF>(a, lds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+size_t stage32_lds_bytes(int p, int E, int Q, bool bf16) {
+  const int N1 = p + 1, NP = N1 * N1;
+  return (size_t)lds32_layout(NP, N1, NP | 1, E, Q, bf16).total * sizeof(double);
+}
+
+bool bf16_contraction_available(int p) { return false && p > 0; }
+
+hipError_t launch_stage32(int p, const Stage32Args &a, size_t lds, int contract, hipStream_t st) {
+  if (contract) return hipErrorInvalidValue;
+  return launch32_b<false>(p, a, lds, st);
+}
+
+hipError_t launch_to_dev32(const double *src, float *dst, const double *vel, int K, int Np, int Q,
+                           double offset, hipStream_t st) {
+  const size_t KNP = (size_t)K * Np;
+  dim3 grid((unsigned)((KNP + 255) / 256), (unsigned)Q);
+  hipLaunchKernelGGL(to_dev32_kernel, grid, dim3(256), 0, st, src, dst, vel, KNP, Np, Q, offset);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_dev32(const float *src, double *dst, const double *vel, int K, int Np, int Q,
+                             double offset, hipStream_t st) {
+  const size_t KNP = (size_t)K * Np;
+  dim3 grid((unsigned)((KNP + 255) / 256), (unsigned)Q);
+  hipLaunchKernelGGL(from_dev32_kernel, grid, dim3(256), 0, st, src, dst, vel, KNP, Np, Q, offset);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_equilibrium32(float *g, const double *vel, int K, int Np, int Q, double rho0,
+                                     double ux0, double uy0, double theta, double rho_ref,
+                                     hipStream_t st) {
+  const size_t KNP = (size_t)K * Np;
+  dim3 grid((unsigned)((KNP + 255) / 256), (unsigned)Q);
+  hipLaunchKernelGGL(init_equilibrium32_kernel, grid, dim3(256), 0, st, g, vel, KNP, Np, Q, rho0,
+                     ux0, uy0, theta, rho_ref);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments32(const float *g, const double *vel, int K, int Np, int Q, double rho_ref,
+                            double *rho, double *ux, double *uy, hipStream_t st) {
+  const size_t KNP = (size_t)K * Np;
+  hipLaunchKernelGGL(moments32_kernel, dim3((unsigned)((KNP + 255) / 256)), dim3(256), 0, st, g,
+                     vel, KNP, Np, Q, rho_ref, rho, ux, uy);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual32(const float *k, const double *vel, int K, int Np, int Q, double scale,
+                             unsigned long long *result, hipStream_t st) {
+  const size_t KNP = (size_t)K * Np;
+  hipLaunchKernelGGL(residual32_kernel, dim3((unsigned)((KNP + 255) / 256)), dim3(256), 0, st, k,
+                     vel, KNP, Np, Q, scale, result);
+  return hipGetLastError();
+}
+
+}  // namespace dgbgk

@@ -87,6 +87,32 @@ def test_required_bytes():
     assert n >= 4 * 16_777_216 * 8
 
 
+def test_precision_choices():
+    spec = workloads.CAVITY_128x128_P4_NC24_KN8
+    vel = binding.velocity_set(spec.velset)
+    ndof = 128 * 128 * 25 * 576
+    n64 = binding.required_bytes(spec.nx, spec.ny, spec.p, vel, 6.4, spec.bc, spec.wall_u)
+    n32 = binding.required_bytes(spec.nx, spec.ny, spec.p, vel, 6.4, spec.bc, spec.wall_u,
+                                 precision="fp32")
+    assert n64 >= 4 * ndof * 8
+    # four FP32 registers and one FP64 transfer buffer
+    assert 4 * ndof * 4 + ndof * 8 <= n32 < n64
+    s = binding.Solver.from_spec(spec, precision=binding.FP32)
+    t = s.tiling()
+    assert t["fused"] and not t["persistent"] and t["elems_per_group"] == 1
+    assert t["lds_bytes"] <= 64 * 1024
+    with pytest.raises(binding.DgbgkError) as ei:
+        s.set_tiling(2, 48)
+    assert ei.value.code == binding.ENOTSUP
+    with pytest.raises(binding.DgbgkError) as ei:
+        binding.Solver.from_spec(spec, precision=7)
+    assert ei.value.code == binding.EINVAL
+    # no device: device calls of an FP32 solver fail loudly as well
+    with pytest.raises(binding.DgbgkError) as ei:
+        s.init_equilibrium()
+    assert ei.value.code == binding.EDEVICE
+
+
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(p=0), dict(p=9), dict(tau=-1.0), dict(tau=0.0),
     dict(bc=(0, 1, 1, 1)),                                   # unpaired periodic side

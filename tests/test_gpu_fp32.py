@@ -1,0 +1,219 @@
+"""GPU parity of the FP32-storage precision path (the state streamed in FP32 as
+the deviation from w_q rho_ref; moments, wall densities and residual in FP64)
+against the FP64 CPU oracle on the same seeded inputs, and against the GPU
+FP64 path at the full precision-workload size.
+
+Bar: 1e-5 relative in max-norm on rho and u (normwise over nodes and
+components for u, as in the FP64 tests) after the same RK4 steps, and on the
+right-hand side itself."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from paper_2012_13487_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _moment_errors(mg, mo):
+    (rg, uxg, uyg), (ro, uxo, uyo) = mg, mo
+    u_g = np.stack([uxg, uyg])
+    u_o = np.stack([uxo, uyo])
+    return _rel(rg, ro), float(np.max(np.abs(u_g - u_o)) / max(np.max(np.abs(u_o)), 1e-300))
+
+
+def _pair(oracle_mod, spec, **kw):
+    g = binding.Solver.from_spec(spec, precision=binding.FP32, **kw)
+    o = oracle_mod.Oracle.from_spec(spec)
+    assert g.shape == o.shape
+    return g, o
+
+
+RHS_CASES = [
+    ("couette_8x8_p2_gh4", workloads.couette(nx=8, ny=8, p=2)),
+    ("cavity_6x5_p3_nc8", workloads.cavity(n=6, ny=5, p=3, m=8, lid=0.1)),
+    ("cavity_5x3_p4_nc5_scalar", workloads.cavity(n=5, ny=3, p=4, m=5, lid=0.2)),  # Q Np odd
+    ("periodic_7x3_p1_gh3", workloads.periodic_box(nx=7, ny=3, p=1, velset=("gh", 3), kn=0.3)),
+    ("cavity_9x7_p3_nc9", workloads.cavity(n=9, ny=7, p=3, m=9, lid=0.15)),
+    ("cavity_3x2_p6_nc4", workloads.cavity(n=3, ny=2, p=6, m=4)),
+    ("collisionless_4x4_p3", workloads.periodic_box(nx=4, ny=4, p=3, tau=float("inf"))),
+]
+
+
+@pytest.mark.parametrize("name,spec", RHS_CASES, ids=[c[0] for c in RHS_CASES])
+def test_fp32_rhs_parity(oracle_mod, name, spec):
+    _say(f"[gpu] fp32 rhs parity {name}")
+    g, o = _pair(oracle_mod, spec)
+    assert g.tiling()["fused"]
+    f = workloads.perturbed_state(17, o.w, o.K, o.Np, amp=0.2)
+    kg = g.rhs(f)
+    ko = o.rhs(f)
+    assert np.isfinite(kg).all()
+    assert _rel(kg, ko) < TOL32, (name, _rel(kg, ko))
+
+
+@pytest.mark.parametrize("name,spec", RHS_CASES[:3], ids=[c[0] for c in RHS_CASES[:3]])
+def test_fp32_wall_density_parity(oracle_mod, name, spec):
+    # the wall densities are reduced in FP64 from the FP32 deviation; only the
+    # rounding of the stored deviation remains
+    _say(f"[gpu] fp32 wall density {name}")
+    g, o = _pair(oracle_mod, spec)
+    f = workloads.perturbed_state(5, o.w, o.K, o.Np, amp=0.2)
+    wg = g.wall_density(f)
+    wo = o.wall_density(f)
+    wall = o.operator(7).astype(int) < 0
+    if wall.any():
+        assert _rel(wg[wall], wo[wall]) < 1e-7
+    assert np.all(wg[~wall] == 0.0)
+
+
+def test_fp32_state_round_trip_and_moments(oracle_mod):
+    # set_state / get_state go through the FP32 deviation: exact to the
+    # rounding of g; moments are FP64 sums of the stored values
+    _say("[gpu] fp32 state round trip")
+    spec = workloads.cavity(n=5, p=3, m=8)
+    g, o = _pair(oracle_mod, spec)
+    f = workloads.perturbed_state(2, o.w, o.K, o.Np, amp=0.1)
+    g.set_state(f)
+    dev = f - o.w[:, None, None]
+    back = g.get_state() - o.w[:, None, None]
+    assert np.max(np.abs(back - dev)) <= 2.0 ** -24 * np.max(np.abs(dev))
+    o.set_state(f)
+    er, eu = _moment_errors(g.moments(), o.moments())
+    assert er < 1e-8 and eu < 1e-6
+
+
+def test_fp32_couette_200_steps(oracle_mod):
+    _say("[gpu] fp32 couette 8x8 p2 200 steps")
+    spec = workloads.COUETTE_8x8_P2_D2Q16
+    g, o = _pair(oracle_mod, spec)
+    dt = o.stable_dt(spec.cfl)
+    g.init_equilibrium()
+    o.init_equilibrium()
+    g.step(spec.steps, dt)
+    o.rk4(spec.steps, dt)
+    er, eu = _moment_errors(g.moments(), o.moments())
+    _say(f"  err rho {er:.2e} u {eu:.2e}")
+    assert er < TOL32 and eu < TOL32, (er, eu)
+
+
+def test_fp32_cavity_perturbed_steps(oracle_mod):
+    _say("[gpu] fp32 cavity 10x7 p3 nc10 perturbed 40 steps")
+    spec = workloads.cavity(n=10, ny=7, p=3, m=10, lid=0.1, kn=0.5)
+    g, o = _pair(oracle_mod, spec)
+    f = workloads.perturbed_state(23, o.w, o.K, o.Np, amp=0.05)
+    g.set_state(f)
+    o.set_state(f)
+    dt = o.stable_dt(0.2)
+    g.step(40, dt)
+    o.rk4(40, dt)
+    er, eu = _moment_errors(g.moments(), o.moments())
+    _say(f"  err rho {er:.2e} u {eu:.2e}")
+    assert er < TOL32 and eu < TOL32, (er, eu)
+
+
+def test_fp32_precision_workload_small_mesh(oracle_mod):
+    """The precision workload's physics (cavity, Kn = 8, p = 4, NC 24 x 24) on an
+    8 x 8 mesh: rho, u after 10 RK4 steps from rest against the oracle."""
+    _say("[gpu] fp32 cavity 8x8 p4 nc24 kn8, 10 steps")
+    spec = workloads.CAVITY_128x128_P4_NC24_KN8.with_(nx=8, ny=8)
+    g, o = _pair(oracle_mod, spec)
+    dt = o.stable_dt(spec.cfl)
+    g.init_equilibrium()
+    o.init_equilibrium()
+    g.step(10, dt)
+    o.rk4(10, dt)
+    er, eu = _moment_errors(g.moments(), o.moments())
+    _say(f"  err rho {er:.2e} u {eu:.2e}")
+    assert er < TOL32 and eu < TOL32, (er, eu)
+
+
+def test_fp32_mass_conservation():
+    _say("[gpu] fp32 mass conservation")
+    spec = workloads.cavity(n=8, p=3, m=10, lid=0.1, kn=0.5)
+    g = binding.Solver.from_spec(spec, precision="fp32")
+    M = np.kron(g.operator(5), g.operator(5))
+    J = (1 / 8) ** 2 / 4
+    f = workloads.perturbed_state(8, g.w, g.K, g.Np, amp=0.1)
+    g.set_state(f)
+    m0 = J * np.einsum("n,kn->", M.sum(axis=0), g.moments()[0])
+    g.step(300, g.stable_dt(0.2))
+    m1 = J * np.einsum("n,kn->", M.sum(axis=0), g.moments()[0])
+    # the deviation form conserves mass up to FP32 rounding of the deviation
+    assert abs(m1 - m0) < 1e-7 * m0
+
+
+def test_fp32_residual_and_determinism(oracle_mod):
+    _say("[gpu] fp32 residual / determinism")
+    spec = workloads.cavity(n=6, p=2, m=8, lid=0.1)
+    g, o = _pair(oracle_mod, spec)
+    f = workloads.perturbed_state(3, o.w, o.K, o.Np, amp=0.1)
+    g.set_state(f)
+    o.set_state(f)
+    rg = g.residual()
+    ro, rc = o.residual()
+    assert rc == 0 and abs(rg - ro) < TOL32 * ro
+    outs = []
+    for _ in range(2):
+        h = binding.Solver.from_spec(spec, precision=binding.FP32)
+        h.init_equilibrium()
+        h.step(50, h.stable_dt(0.2))
+        outs.append(h.get_state())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_fp32_full_size_precision_workload(oracle_mod):
+    """128 x 128 quads, p = 4, NC 24 x 24, Kn = 8 (235.9 M DOF) in the launch
+    configuration the benchmark times: the right-hand side of a perturbed
+    state against the oracle, and rho, u after 10 RK4 steps from rest against
+    the oracle."""
+    _say("[gpu] fp32 full-size cavity 128x128 p4 nc24 kn8")
+    spec = workloads.CAVITY_128x128_P4_NC24_KN8
+    g, o = _pair(oracle_mod, spec, stream="torch", torch_memory=True)
+    f = workloads.perturbed_state(41, o.w, o.K, o.Np, amp=0.05)
+    _say("  rhs")
+    assert _rel(g.rhs(f), o.rhs(f)) < TOL32
+    del f
+    dt = o.stable_dt(spec.cfl)
+    g.init_equilibrium()
+    o.init_equilibrium()
+    _say("  10 steps")
+    g.step(10, dt)
+    o.rk4(10, dt)
+    er, eu = _moment_errors(g.moments(), o.moments())
+    _say(f"  err rho {er:.2e} u {eu:.2e}")
+    assert er < TOL32 and eu < TOL32, (er, eu)
+
+
+def test_fp32_against_fp64_gpu_after_2000_steps():
+    """The precision workload on the GPU in FP32 and in FP64 from rest, 2000
+    RK4 steps each: rho, u agree to the FP32 bar."""
+    _say("[gpu] fp32 vs fp64 cavity 128x128 p4 nc24 kn8, 2000 steps")
+    spec = workloads.CAVITY_128x128_P4_NC24_KN8
+    res = []
+    for prec in (binding.FP64, binding.FP32):
+        g = binding.Solver.from_spec(spec, precision=prec, stream="torch", torch_memory=True)
+        dt = g.stable_dt(spec.cfl)
+        g.init_equilibrium()
+        for _ in range(4):
+            g.step(500, dt)
+            g.synchronize()
+            _say(f"  prec {prec}: {g.steps_taken()} steps")
+        res.append(g.moments())
+        g.close()
+    er, eu = _moment_errors(res[1], res[0])
+    _say(f"  err rho {er:.2e} u {eu:.2e}")
+    assert er < TOL32 and eu < TOL32, (er, eu)
