@@ -95,9 +95,10 @@ def precision_path(steps_small, steps_big):
     from paper_2012_13487_amd import Solver
     out = {}
     for key, spec, steps, precs in (
-            ("cavity64x64_p3_nc16", workloads.CAVITY_64x64_P3_NC16, steps_small, ("fp32",)),
+            ("cavity64x64_p3_nc16", workloads.CAVITY_64x64_P3_NC16, steps_small,
+             ("fp32", "fp32_bf16mma")),
             ("cavity128x128_p4_nc24_kn8", workloads.CAVITY_128x128_P4_NC24_KN8, steps_big,
-             ("fp32", "fp64"))):
+             ("fp32", "fp32_bf16mma", "fp64"))):
         entry = {}
         for prec in precs:
             g = Solver.from_spec(spec, precision=prec, stream="torch", torch_memory=True)
@@ -106,7 +107,7 @@ def precision_path(steps_small, steps_big):
             time_steps(g, 2, dt)
             ms = time_steps(g, steps, dt)
             stage_us = 1000.0 * ms / (4 * steps)
-            bpd = ALG_BYTES_PER_DOF_STAGE_FP32 if prec == "fp32" else ALG_BYTES_PER_DOF_STAGE
+            bpd = ALG_BYTES_PER_DOF_STAGE if prec == "fp64" else ALG_BYTES_PER_DOF_STAGE_FP32
             ach = bpd * g.ndof / (stage_us * 1e-6) / 1e9
             entry["dof"] = g.ndof
             entry[prec] = {"value": g.ndof * 4 * steps / (ms / 1000.0), "unit": "DOF-updates/s",
@@ -117,8 +118,11 @@ def precision_path(steps_small, steps_big):
         out[key] = entry
     big = out["cavity128x128_p4_nc24_kn8"]
     out["fp32_over_fp64_precision_workload"] = big["fp32"]["value"] / big["fp64"]["value"]
-    out["note"] = ("FP32 = state stored as the FP32 deviation from w_q; moments, wall densities and "
-                   "residual in FP64; error vs the FP64 oracle measured by the GPU tests (<= 1e-5)")
+    out["bf16_over_fp64_precision_workload"] = big["fp32_bf16mma"]["value"] / big["fp64"]["value"]
+    out["note"] = ("fp32 = state stored as the FP32 deviation from w_q; moments, wall densities and "
+                   "residual in FP64 (error vs the FP64 oracle <= 1e-5 in the GPU tests); "
+                   "fp32_bf16mma = the same with the volume contractions on bf16 matrix cores "
+                   "(<= 2e-3)")
     return out
 
 

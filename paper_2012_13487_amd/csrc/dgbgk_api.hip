@@ -30,7 +30,7 @@ constexpr int kMaxQ = 4096;
 size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t fn, acc, a, b, xfer, vel, feqb, wmom, mom, rhow, u64, total;
+  size_t fn, acc, a, b, xfer, vel, feqb, wmom, dmat, mom, rhow, u64, total;
 };
 
 bool is_fp32(int precision) { return precision == DGBGK_FP32 || precision == DGBGK_FP32_BF16MMA; }
@@ -53,6 +53,7 @@ Layout make_layout(int64_t K, int Np, int Nfp, int Q, int precision) {
   L.mom = off;  off += round_up((size_t)3 * K * Np * sizeof(double));
   L.rhow = off; off += round_up((size_t)K * 4 * Nfp * sizeof(double));
   L.u64 = off;  off += round_up(8 * sizeof(unsigned long long));
+  L.dmat = off; off += round_up((size_t)((2 * Np + 15) / 16) * 16 * 32 * sizeof(uint16_t));
   L.total = off;
   return L;
 }
@@ -82,6 +83,7 @@ struct dgbgk_solver {
   double *d_fn = nullptr, *d_acc = nullptr, *d_a = nullptr, *d_b = nullptr;  // FP64 states
   float *g_fn = nullptr, *g_acc = nullptr, *g_a = nullptr, *g_b = nullptr;   // FP32 deviations
   double *d_xfer = nullptr;  // FP64 staging of host transfers (FP32 precisions)
+  uint16_t *d_dmat = nullptr;  // bf16 [Dr; Ds] rows, 32 columns (FP32_BF16MMA)
   int prec = DGBGK_FP64;
   double rho_ref = 1.0;      // reference density of the FP32 deviation g = f - w rho_ref
   double mconst[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -252,6 +254,7 @@ int ensure_device(dgbgk_solver *s) {
   s->d_vel = (double *)(b + s->lay.vel);
   s->d_feqb = (double *)(b + s->lay.feqb);
   s->d_wmom = (double *)(b + s->lay.wmom);
+  s->d_dmat = (uint16_t *)(b + s->lay.dmat);
   s->d_mom = (double *)(b + s->lay.mom);
   s->d_rhow = (double *)(b + s->lay.rhow);
   s->d_u64 = (unsigned long long *)(b + s->lay.u64);
@@ -283,6 +286,29 @@ int ensure_device(dgbgk_solver *s) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(s->d_feqb, s->feqb.data(), s->feqb.size() * sizeof(double),
                        hipMemcpyHostToDevice, s->stream);
+  std::vector<uint16_t> dm;
+  if (s->prec == DGBGK_FP32_BF16MMA) {
+    // [Dr; Ds] (2 Np x Np, node n = i + N1 j), rows padded to 16-row tiles and
+    // columns to 32, rounded to bf16 (nearest, ties to even)
+    const int N1 = s->Nfp, Np = s->Np, rows = (2 * Np + 15) / 16 * 16;
+    dm.assign((size_t)rows * 32, 0);
+    auto bf = [](double v) {
+      float x = (float)v;
+      uint32_t u;
+      std::memcpy(&u, &x, 4);
+      u += 0x7fffu + ((u >> 16) & 1u);
+      return (uint16_t)(u >> 16);
+    };
+    for (int n = 0; n < Np; ++n)
+      for (int m = 0; m < Np; ++m) {
+        const int in = n % N1, jn = n / N1, im = m % N1, jm = m / N1;
+        if (jn == jm) dm[(size_t)n * 32 + m] = bf(s->D1[in * N1 + im]);
+        if (in == im) dm[(size_t)(Np + n) * 32 + m] = bf(s->D1[jn * N1 + jm]);
+      }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->d_dmat, dm.data(), dm.size() * sizeof(uint16_t), hipMemcpyHostToDevice,
+                         s->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "uploading tables");
   s->dev_ready = true;
@@ -339,6 +365,7 @@ Stage32Args base_args32(const dgbgk_solver *s) {
   a.vel = s->d_vel;
   a.feqb = s->d_feqb;
   a.wmom = s->d_wmom;
+  a.dmat = s->prec == DGBGK_FP32_BF16MMA ? s->d_dmat : nullptr;
   a.rx = (float)(2.0 / s->hx);
   a.sy = (float)(2.0 / s->hy);
   a.fsx = (float)(2.0 / s->hx);

@@ -57,8 +57,9 @@ __host__ __device__ inline Lds32 lds32_layout(int NP, int NFP, int S, int E, int
   L.rw = L.mom + E * NP * 4;
   L.nbr = L.rw + E * 4 * NFP;
   L.vol = (L.nbr + (E * 4 + 1) / 2 + 3) / 4 * 4;
-  // bf16: per wavefront a [2 NP][16] float block (Dr g and Ds g of 16 velocities)
-  L.total = L.vol + (bf16 ? 4 * (2 * NP * 16) / 2 : 0);
+  // bf16: per wavefront a [2 NP][16] float block (Dr g and Ds g of 16
+  // velocity rows) and the 64 row means of its rows
+  L.total = L.vol + (bf16 ? (4 * (2 * NP * 16) + 4 * 64) / 2 : 0);
   return L;
 }
 
@@ -92,11 +93,59 @@ __device__ __forceinline__ float rk32(float kv, float x, float y, float ca, floa
   return x + (y + ca * kv);
 }
 
-// Round-to-nearest-even FP32 -> bf16 bits.
-__device__ __forceinline__ uint16_t bf16_bits(float v) {
-  uint32_t u = __float_as_uint(v);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+typedef float float4m __attribute__((ext_vector_type(4)));
+
+// Volume term of the wavefront's 64 rows r0 + 64 w + lane on bf16 matrix
+// cores.  The rows go in four groups of 16 velocity rows (the N dimension of
+// v_mfma_f32_16x16x32_bf16); the M dimension runs over the 2 NP output nodes of
+// [Dr; Ds] (MT tiles of 16), the K dimension over the NP input nodes (padded to
+// 32).  Each row's mean is subtracted before rounding to bf16 (Dr and Ds
+// annihilate constants), so the rounding is relative to the variation of g
+// within the element.  Lane layout (established with an in-bounds probe):
+// A: lane l holds A[l % 16][8 (l / 16) + t]; B: B[8 (l / 16) + t][l % 16];
+// D: register v of lane l is D[4 (l / 16) + v][l % 16].  Results go through a
+// per-wavefront LDS block to the lane that owns the row; the LDS accesses of
+// one wavefront execute in order, so no barrier is needed.
+template <int NP, int MT>
+__device__ __forceinline__ void volume_bf16(const float *tile, int S, int r0w, int rows, bool own_valid,
+                                            const float (&f)[NP], float ax, float ay,
+                                            const bf16x8 (&dA)[MT], float *cm, float *vs,
+                                            float (&kk)[NP]) {
+  const int lane = threadIdx.x & 63;
+  float mean = 0.0f;
+  if (own_valid) {
+#pragma unroll
+    for (int n = 0; n < NP; ++n) mean += f[n];
+    mean *= 1.0f / NP;
+  }
+  cm[lane] = mean;
+  const int col = lane & 15, kg = lane >> 4;
+#pragma unroll
+  for (int gi = 0; gi < 4; ++gi) {
+    const int rb = r0w + 16 * gi + col;  // row of this lane's B column
+    bf16x8 bop;
+    const float cmb = cm[16 * gi + col];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int n = 8 * kg + t;
+      const float v = (rb < rows && n < NP) ? tile[rb * S + n] - cmb : 0.0f;
+      bop[t] = (__bf16)v;
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      float4m d = {0.0f, 0.0f, 0.0f, 0.0f};
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dA[mt], bop, d, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * mt + 4 * kg + v;
+        if (row < 2 * NP) vs[row * 16 + col] = d[v];
+      }
+    }
+    if (kg == gi && own_valid) {
+#pragma unroll
+      for (int n = 0; n < NP; ++n) kk[n] = -(ax * vs[n * 16 + col] + ay * vs[(NP + n) * 16 + col]);
+    }
+  }
 }
 
 // MODE: 0 writes L(f_s); 1 first RK4 stage; 2 second and third; 4 fourth.
@@ -241,12 +290,37 @@ __global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) 
 
   // ---- 3. per velocity row: L(f) in FP32 ------------------------------------------
   const int rows = E * Q;
+  constexpr int MT = (2 * NP + 15) / 16;  // bf16: M tiles of [Dr; Ds]
+  bf16x8 dA[BF ? MT : 1];
+  if constexpr (BF) {
+    const int lane = tid & 63;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+      dA[mt] = *reinterpret_cast<const bf16x8 *>(a.dmat + (size_t)(16 * mt + (lane & 15)) * 32 +
+                                                 8 * (lane >> 4));
+  }
   for (int r0 = 0; r0 < rows; r0 += nthr) {
     const int r = r0 + tid;
-    if (r >= rows) continue;
     const int e = r / Q, q = r - e * Q;
-    if (e >= Eb) continue;
-    const float cx = (float)a.vel[q], cy = (float)a.vel[Q + q], wq = (float)a.vel[2 * Q + q];
+    const bool valid = r < rows && e < Eb;
+    float f[NP];
+    float kk[NP];
+    if (valid) {
+      const float *row = tile + r * S;
+#pragma unroll
+      for (int c = 0; c < NP; ++c) f[c] = row[c];
+    }
+    const int qv = valid ? q : 0;
+    const float cx = (float)a.vel[qv], cy = (float)a.vel[Q + qv], wq = (float)a.vel[2 * Q + qv];
+    const float ax = cx * a.rx, ay = cy * a.sy;
+    if constexpr (BF) {
+      // all lanes take part in the matrix-core products
+      const int wave = tid >> 6;
+      float *vs = (float *)(lds + L.vol) + wave * (2 * NP * 16);
+      float *cm = (float *)(lds + L.vol) + 4 * (2 * NP * 16) + wave * 64;
+      volume_bf16<NP, MT>(tile, S, r0 + 64 * wave, rows, valid, f, ax, ay, dA, cm, vs, kk);
+    }
+    if (!valid) continue;
     const int fxc = cx > 0.0f ? 3 : 1, fyc = cy > 0.0f ? 0 : 2;  // inflow faces
     const int nbx = nbr[e * 4 + fxc], nby = nbr[e * 4 + fyc];
     // exterior traces of the two inflow faces
@@ -261,24 +335,20 @@ __global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) 
         py[m] = gy ? sy[m] : 0.0f;
       }
     }
-    float f[NP];
-    const float *row = tile + r * S;
+    if constexpr (!BF) {
 #pragma unroll
-    for (int c = 0; c < NP; ++c) f[c] = row[c];
-    float kk[NP];
-    const float ax = cx * a.rx, ay = cy * a.sy;
+      for (int j = 0; j < N1; ++j)
 #pragma unroll
-    for (int j = 0; j < N1; ++j)
+        for (int i = 0; i < N1; ++i) {
+          float dr = 0.0f, ds = 0.0f;
 #pragma unroll
-      for (int i = 0; i < N1; ++i) {
-        float dr = 0.0f, ds = 0.0f;
-#pragma unroll
-        for (int m = 0; m < N1; ++m) {
-          dr += a.D1[i * N1 + m] * f[m + N1 * j];
-          ds += a.D1[j * N1 + m] * f[i + N1 * m];
+          for (int m = 0; m < N1; ++m) {
+            dr += a.D1[i * N1 + m] * f[m + N1 * j];
+            ds += a.D1[j * N1 + m] * f[i + N1 * m];
+          }
+          kk[i + N1 * j] = -(ax * dr + ay * ds);
         }
-        kk[i + N1 * j] = -(ax * dr + ay * ds);
-      }
+    }
     // wall exterior state in deviation form, rho_w f^eq_q(1, u_b) - w_q rho_ref (FP64)
     const double wrr = a.vel[2 * Q + q] * a.rho_ref;
     if (cx != 0.0f) {
@@ -508,11 +578,18 @@ size_t stage32_lds_bytes(int p, int E, int Q, bool bf16) {
   return (size_t)lds32_layout(NP, N1, NP | 1, E, Q, bf16).total * sizeof(double);
 }
 
-bool bf16_contraction_available(int p) { return false && p > 0; }
+bool bf16_contraction_available(int p) { return p >= 1 && p <= 4; }
 
 hipError_t launch_stage32(int p, const Stage32Args &a, size_t lds, int contract, hipStream_t st) {
-  if (contract) return hipErrorInvalidValue;
-  return launch32_b<false>(p, a, lds, st);
+  if (!contract) return launch32_b<false>(p, a, lds, st);
+  if (!a.dmat) return hipErrorInvalidValue;
+  switch (p) {
+    case 1: return launch32_pb<1, true>(a, lds, st);
+    case 2: return launch32_pb<2, true>(a, lds, st);
+    case 3: return launch32_pb<3, true>(a, lds, st);
+    case 4: return launch32_pb<4, true>(a, lds, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_to_dev32(const double *src, float *dst, const double *vel, int K, int Np, int Q,

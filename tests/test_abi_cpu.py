@@ -107,6 +107,11 @@ def test_precision_choices():
     with pytest.raises(binding.DgbgkError) as ei:
         binding.Solver.from_spec(spec, precision=7)
     assert ei.value.code == binding.EINVAL
+    b = binding.Solver.from_spec(spec, precision="fp32_bf16mma")
+    assert b.tiling()["lds_bytes"] <= 80 * 1024
+    with pytest.raises(binding.DgbgkError) as ei:  # bf16 contractions: p <= 4
+        binding.Solver.from_spec(workloads.cavity(n=2, p=5, m=4), precision="fp32_bf16mma")
+    assert ei.value.code == binding.ENOTSUP
     # no device: device calls of an FP32 solver fail loudly as well
     with pytest.raises(binding.DgbgkError) as ei:
         s.init_equilibrium()
