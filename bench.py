@@ -126,6 +126,83 @@ def precision_path(steps_small, steps_big):
     return out
 
 
+def batching(steps):
+    """The 64-problem mixed batch (seed 0): aggregate DOF-updates/s of the
+    problems stepped one after another by the single-problem path (FP64, each
+    in its default decomposition), and of the persistent batched kernels with
+    hipGraph-replayed RK4 steps in FP64 and in FP32 storage."""
+    import numpy as np
+    import workloads
+    from paper_2012_13487_amd import Batch, Solver
+
+    specs = workloads.batch_instances(seed=0, n=64)
+    out = {"workload": "64 mixed problems, seed 0: Couette or cavity, N x N quads with N in "
+                       "16..96, p in 2..4, Kn log-uniform in [0.1, 10], D2Q16 GH or NC MxM, "
+                       "M in 8..24",
+           "steps": steps}
+
+    def run(prec, batched):
+        solvers = [Solver.from_spec(sp, precision=prec, stream="torch", torch_memory=True)
+                   for sp in specs]
+        for g in solvers:
+            g.init_equilibrium()
+        tuned = {}
+        if batched:
+            # the autotuner, once per (precision, p, Q) class; members of a
+            # batch run the fused form
+            for g, sp in zip(solvers, specs):
+                key = (g.p, g.Q)
+                g.set_tiling(1)
+                if key not in tuned:
+                    g.autotune(3)
+                    tuned[key] = g.tiling()["elems_per_group"]
+                else:
+                    g.set_block_elements(tuned[key])
+        dts = np.array([g.stable_dt(sp.cfl) for g, sp in zip(solvers, specs)])
+        dof = sum(g.ndof for g in solvers)
+        if batched:
+            b = Batch(solvers, stream="torch", graph=True)
+            b.step(1, dts)  # builds the graph
+            ms = _timed(lambda: b.step(steps, dts))
+            launches = b.launches_per_step()
+            b.close()
+        else:
+            for g, dt in zip(solvers, dts):
+                g.step(1, dt)
+            ms = _timed(lambda: [g.step(steps, dt) for g, dt in zip(solvers, dts)])
+            launches = 4 * len(solvers)
+        for g in solvers:
+            g.close()
+        res = {"value": dof * 4 * steps / (ms / 1000.0), "unit": "DOF-updates/s",
+               "ms_per_step": ms / steps, "launches_per_step": launches}
+        if tuned:
+            res["autotuned_elems_per_group"] = {f"p{p}_Q{q}": e for (p, q), e in sorted(tuned.items())}
+        return res, dof
+
+    out["sequential_fp64"], out["dof"] = run("fp64", False)
+    out["batched_fp64_graph"], _ = run("fp64", True)
+    out["batched_fp32_graph"], _ = run("fp32", True)
+    out["batched_fp64_over_sequential"] = (out["batched_fp64_graph"]["value"]
+                                           / out["sequential_fp64"]["value"])
+    out["batched_fp32_over_sequential_fp64"] = (out["batched_fp32_graph"]["value"]
+                                                / out["sequential_fp64"]["value"])
+    return out
+
+
+def _timed(fn):
+    """Milliseconds of the device work `fn` enqueues on torch's current stream."""
+    import torch
+    stream = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +212,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-path", action="store_true")
+    ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB (5 times), to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters of the stage kernel")
@@ -236,6 +314,8 @@ def main():
     del g
     if not args.no_precision_path:
         out["precision_path"] = precision_path(100, 20)
+    if not args.no_batching:
+        out["batching"] = batching(10)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_budget)
     print(json.dumps(out), flush=True)

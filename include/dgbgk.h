@@ -228,6 +228,63 @@ int dgbgk_get_tiling(const dgbgk_solver *s, int32_t *fused, int32_t *elems_per_g
 /* Number of RK4 steps taken since the last init / set_state. */
 int dgbgk_steps_taken(const dgbgk_solver *s, int64_t *steps);
 
+/* Elements per work-group of the fused forms (0 = automatic).  The value must
+ * divide into a tile that fits in LDS; DGBGK_EINVAL otherwise (the previous
+ * choice is kept).  Changing it changes the summation order of the node
+ * moments, so results agree with other choices to rounding, not bit for bit. */
+int dgbgk_set_block_elements(dgbgk_solver *s, int32_t elems_per_group);
+
+/* Autotuner: times `launches` right-hand-side launches on the current state
+ * (the state is not modified) for every admissible number of elements per
+ * work-group of the fused form (and, in FP64, velocity tiles of Q, Q/2, ...,
+ * unless the caller forced the fused form with dgbgk_set_tiling mode 1 or 3),
+ * keeps the fastest and returns its average launch time in microseconds
+ * (optional).  Requires a state (DGBGK_ESTATE otherwise); synchronises the
+ * solver's stream. */
+int dgbgk_autotune(dgbgk_solver *s, int32_t launches, double *best_us);
+
+/* ---- batches: several problems advanced together ------------------------
+ *
+ * A batch advances n solvers (any mix of meshes, orders, velocity sets, Kn,
+ * walls and precisions) in lock step: each RK4 stage is one persistent kernel
+ * launch per class of (precision, order p, access width, LDS size) that walks
+ * a device work list of (problem, element block) items and reads each
+ * problem's arguments (state pointers, mesh and velocity tables, tau, walls,
+ * and its own dt) from a device descriptor table.  The members keep their own
+ * device memory and states; while they are in a batch, use the batch to step
+ * them.  Each member's result is bit-identical to stepping it alone with the
+ * same work decomposition (batch invariance).  Members use the fused form (all
+ * velocities of a block of elements per work-group); a member whose fused tile
+ * does not fit in LDS is rejected (DGBGK_ENOTSUP).  The solvers must outlive
+ * the batch. */
+typedef struct dgbgk_batch dgbgk_batch;
+
+/* Builds work lists and descriptor tables on the device (the members' device
+ * memory is set up if it is not yet).  hip_stream: stream for all batch work
+ * (NULL = null stream). */
+int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream,
+                       dgbgk_batch **out);
+
+/* use_graph != 0: each RK4 step of the batch is captured once in a hipGraph
+ * and replayed (re-captured when the membership changes, not when dt does:
+ * the descriptors are device data). */
+int dgbgk_batch_set_graph(dgbgk_batch *b, int32_t use_graph);
+
+/* nsteps RK4 steps of every member; dt[i] is member i's time step (n values,
+ * host array).  Enqueues only.  Every member needs a state (DGBGK_ESTATE). */
+int dgbgk_batch_step(dgbgk_batch *b, int64_t nsteps, const double *dt);
+
+/* Steady-state residual of every member (as dgbgk_residual) into r[n]
+ * (host); synchronises.  Non-finite residuals are returned as NaN and the
+ * call returns DGBGK_ENONFINITE after filling all entries. */
+int dgbgk_batch_residuals(dgbgk_batch *b, double *r);
+
+/* Number of persistent launches per RK4 step (classes x 4 stages). */
+int dgbgk_batch_launches_per_step(const dgbgk_batch *b, int32_t *launches);
+
+const char *dgbgk_batch_last_error(const dgbgk_batch *b);
+void dgbgk_batch_destroy(dgbgk_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

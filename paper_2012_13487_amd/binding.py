@@ -70,6 +70,16 @@ SIGNATURES = {
     "dgbgk_get_tiling": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]),
     "dgbgk_steps_taken": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "dgbgk_set_block_elements": (C.c_int, [C.c_void_p, C.c_int32]),
+    "dgbgk_autotune": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
+    "dgbgk_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p,
+                                     C.POINTER(C.c_void_p)]),
+    "dgbgk_batch_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
+    "dgbgk_batch_step": (C.c_int, [C.c_void_p, C.c_int64, _dp]),
+    "dgbgk_batch_residuals": (C.c_int, [C.c_void_p, _dp]),
+    "dgbgk_batch_launches_per_step": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "dgbgk_batch_last_error": (C.c_char_p, [C.c_void_p]),
+    "dgbgk_batch_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None
@@ -105,6 +115,12 @@ def _p(a):
 def _check(rc, handle=None):
     if rc != OK:
         msg = lib().dgbgk_last_error(handle).decode(errors="replace")
+        raise DgbgkError(rc, msg)
+
+
+def _bcheck(rc, handle=None):
+    if rc != OK:
+        msg = lib().dgbgk_batch_last_error(handle).decode(errors="replace")
         raise DgbgkError(rc, msg)
 
 
@@ -257,6 +273,14 @@ class Solver:
     def set_tiling(self, mode, velocities_per_tile=0):
         self._call("dgbgk_set_tiling", mode, velocities_per_tile)
 
+    def set_block_elements(self, elems_per_group):
+        self._call("dgbgk_set_block_elements", int(elems_per_group))
+
+    def autotune(self, launches=5):
+        us = C.c_double()
+        self._call("dgbgk_autotune", int(launches), C.byref(us))
+        return us.value
+
     def tiling(self):
         fused, e, qt, lds = C.c_int32(), C.c_int32(), C.c_int32(), C.c_size_t()
         self._call("dgbgk_get_tiling", C.byref(fused), C.byref(e), C.byref(qt), C.byref(lds))
@@ -319,3 +343,52 @@ class Solver:
         s = C.c_int64()
         self._call("dgbgk_steps_taken", C.byref(s))
         return s.value
+
+
+class Batch:
+    """Several Solvers advanced together by persistent batched kernels (one
+    launch per class of precision / order / tile per RK stage), optionally
+    replaying each RK4 step from a captured hipGraph.  The solvers must
+    outlive the batch."""
+
+    def __init__(self, solvers, stream=None, graph=False):
+        self.solvers = list(solvers)
+        if stream == "torch":
+            import torch  # plumbing only: the stream
+            stream = torch.cuda.current_stream().cuda_stream
+        arr = (C.c_void_p * len(self.solvers))(*[s._h for s in self.solvers])
+        h = C.c_void_p()
+        _bcheck(lib().dgbgk_batch_create(arr, len(self.solvers), C.c_void_p(stream or 0),
+                                         C.byref(h)))
+        self._h = h.value
+        if graph:
+            self.set_graph(True)
+
+    def set_graph(self, on):
+        _bcheck(lib().dgbgk_batch_set_graph(self._h, int(bool(on))), self._h)
+
+    def step(self, nsteps, dt):
+        dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64),
+                                                  (len(self.solvers),)))
+        _bcheck(lib().dgbgk_batch_step(self._h, int(nsteps), _p(dt)), self._h)
+
+    def residuals(self):
+        r = np.zeros(len(self.solvers))
+        _bcheck(lib().dgbgk_batch_residuals(self._h, _p(r)), self._h)
+        return r
+
+    def launches_per_step(self):
+        n = C.c_int32()
+        _bcheck(lib().dgbgk_batch_launches_per_step(self._h, C.byref(n)), self._h)
+        return n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dgbgk_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -95,6 +95,7 @@ struct dgbgk_solver {
   int num_cu = 256;
   size_t lds = 0;
   int tiling_mode = 0, tiling_qt = 0;
+  int forced_E = 0;  // elements per work-group set by the caller or the autotuner (0: automatic)
   // state
   bool have_state = false;
   int64_t steps = 0;
@@ -163,6 +164,7 @@ void choose_tiling32(dgbgk_solver *s) {
   while ((int64_t)E * 2 * s->Q * NP <= 8192 && E * 2 <= s->K &&
          stage32_lds_bytes(s->p, E * 2, s->Q, bf) <= kFusedLdsLimit)
     E *= 2;
+  if (s->forced_E > 0) E = s->forced_E;
   s->E = E;
   s->log2E = 0;
   while ((1 << s->log2E) < E) ++s->log2E;
@@ -189,9 +191,11 @@ void choose_tiling(dgbgk_solver *s) {
   while (E * 2 <= G && (int64_t)E * 2 * s->Q * NP <= 4096 && E * 2 <= s->K &&
          (!row_cap || (int64_t)E * 2 * s->Q <= kBlock))
     E *= 2;
+  if (s->forced_E > 0) E = s->forced_E;
   size_t lds = stage_lds_bytes(s->p, E, s->Q);
   bool fused = lds <= kFusedLdsLimit;
-  if (s->tiling_mode == 1 || s->tiling_mode == 3 || s->tiling_mode == 4) fused = true;
+  if (s->tiling_mode == 1 || s->tiling_mode == 3 || s->tiling_mode == 4 || s->forced_E > 0)
+    fused = true;
   if (s->tiling_mode == 2) fused = false;
   if (fused) {
     s->fused = 1;
@@ -966,6 +970,449 @@ int dgbgk_get_tiling(const dgbgk_solver *s, int32_t *fused, int32_t *elems_per_g
   if (velocities_per_tile) *velocities_per_tile = s->Qt;
   if (lds_bytes) *lds_bytes = s->lds;
   return DGBGK_OK;
+}
+
+}  // extern "C"
+
+// ---- block size, autotuner -----------------------------------------------------
+
+namespace {
+
+// Whether the current configuration of s is one the kernels accept.
+bool tiling_admissible(const dgbgk_solver *s) {
+  if (s->lds > 160 * 1024) return false;
+  if (s->E < 1 || s->E > s->K || (s->E & (s->E - 1)) != 0) return false;
+  if (!is_fp32(s->prec) && s->fused && (int64_t)s->E * s->Np > kBlock) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dgbgk_set_block_elements(dgbgk_solver *s, int32_t elems_per_group) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (elems_per_group < 0) return fail(s, DGBGK_EINVAL, "elems_per_group must be >= 0");
+  const int saved = s->forced_E;
+  s->forced_E = elems_per_group;
+  choose_tiling(s);
+  if (!tiling_admissible(s)) {
+    s->forced_E = saved;
+    choose_tiling(s);
+    return fail(s, DGBGK_EINVAL, "%d elements per work-group: the tile does not fit",
+                elems_per_group);
+  }
+  return DGBGK_OK;
+}
+
+int dgbgk_autotune(dgbgk_solver *s, int32_t launches, double *best_us) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (launches < 1) return fail(s, DGBGK_EINVAL, "launches must be >= 1");
+  if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  // candidates: (forced_E, tiling_mode, tiling_qt)
+  struct Cand { int E, mode, qt; };
+  std::vector<Cand> cands;
+  // a caller that forced the fused form (mode 1 or 3) keeps it
+  const bool fused_only = s->tiling_mode == 1 || s->tiling_mode == 3;
+  const int fmode = fused_only ? s->tiling_mode : 0;
+  for (int E = 1; E <= s->K && E <= 64; E *= 2) cands.push_back({E, fmode, 0});
+  if (!is_fp32(s->prec) && !fused_only)
+    for (int qt = s->Q; qt >= 8; qt = (qt + 1) / 2) cands.push_back({0, 2, qt});
+  const int sE = s->forced_E, sm = s->tiling_mode, sq = s->tiling_qt;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(s, e, "autotune events");
+  double best = -1.0;
+  Cand pick{sE, sm, sq};
+  void *out = s->d_b;  // stage buffer: the state is only read
+  for (const Cand &c : cands) {
+    s->forced_E = c.E;
+    s->tiling_mode = c.mode;
+    s->tiling_qt = c.qt;
+    choose_tiling(s);
+    if (!tiling_admissible(s)) continue;
+    if (c.mode == 2 && s->fused) continue;
+    if ((rc = run_stage(s, 0, s->d_fn, out, 0.0))) break;  // warm-up
+    e = hipEventRecord(e0, s->stream);
+    for (int i = 0; i < launches && e == hipSuccess && !rc; ++i) rc = run_stage(s, 0, s->d_fn, out, 0.0);
+    if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess || rc) break;
+    const double us = 1000.0 * ms / launches;
+    if (best < 0.0 || us < best) {
+      best = us;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s->forced_E = pick.E;
+  s->tiling_mode = pick.mode;
+  s->tiling_qt = pick.qt;
+  choose_tiling(s);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(s, e, "autotune timing");
+  if (best < 0.0) return fail(s, DGBGK_ENOTSUP, "no admissible configuration");
+  if (best_us) *best_us = best;
+  return DGBGK_OK;
+}
+
+}  // extern "C"
+
+// ---- batches ---------------------------------------------------------------------
+
+struct dgbgk_batch {
+  struct Class {
+    int prec = DGBGK_FP64, p = 1, cw = 0, contract = 0, lds_bin = 0;
+    std::vector<int> members;  // indices into s
+    std::vector<int2> items;   // (member index within the class, element block)
+    size_t lds = 0;
+    int groups = 0;
+    size_t off_items = 0, off_desc = 0;  // byte offsets into dev
+    size_t desc_size = 0;                // bytes of one descriptor
+  };
+  std::vector<dgbgk_solver *> s;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<Class> cls;
+  char *dev = nullptr;
+  std::vector<char> host;          // staging of the descriptor tables
+  std::vector<double> dt_loaded;   // dt each member's descriptors hold (NaN: none)
+  bool use_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int bfail(dgbgk_batch *b, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (b) b->err = buf;
+  else g_create_error = buf;
+  return code;
+}
+
+// State buffers a stage reads and writes: 1: fn -> A, 2: A -> B, 3: B -> A,
+// 4: A -> fn, 0 (right-hand side): fn -> B.
+void stage_buffers(dgbgk_solver *s, int stage, void *&fs, void *&out) {
+  void *fn = s->d_fn, *A = s->d_a, *B = s->d_b;
+  switch (stage) {
+    case 1: fs = fn; out = A; break;
+    case 2: fs = A; out = B; break;
+    case 3: fs = B; out = A; break;
+    case 4: fs = A; out = fn; break;
+    default: fs = fn; out = B; break;
+  }
+}
+
+// Fills the host copy of the descriptors of every class, stage and member.
+void fill_descriptors(dgbgk_batch *b, const double *dt) {
+  for (auto &c : b->cls) {
+    const size_t nm = c.members.size();
+    for (int stage = 0; stage <= 4; ++stage)
+      for (size_t i = 0; i < nm; ++i) {
+        dgbgk_solver *s = b->s[c.members[i]];
+        const double h = dt ? dt[c.members[i]] : 0.0;
+        void *fs, *out;
+        stage_buffers(s, stage, fs, out);
+        char *dst = b->host.data() + c.off_desc + ((size_t)stage * nm + i) * c.desc_size;
+        double ca, co;
+        rk_coefficients(stage, h, ca, co);
+        if (is_fp32(s->prec)) {
+          Stage32Args a = base_args32(s);
+          a.fs = (const float *)fs;
+          a.fn = s->g_fn;
+          a.acc = s->g_acc;
+          a.out = (float *)out;
+          a.stage = stage;
+          a.c_acc = (float)ca;
+          a.c_out = (float)co;
+          std::memcpy(dst, &a, sizeof a);
+        } else {
+          StageArgs a = base_args(s);
+          a.fs = (const double *)fs;
+          a.fn = s->d_fn;
+          a.acc = s->d_acc;
+          a.out = (double *)out;
+          a.stage = stage;
+          a.c_acc = ca;
+          a.c_out = co;
+          std::memcpy(dst, &a, sizeof a);
+        }
+      }
+  }
+}
+
+int upload_descriptors(dgbgk_batch *b) {
+  hipError_t e = hipMemcpyAsync(b->dev, b->host.data(), b->host.size(), hipMemcpyHostToDevice,
+                                b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "descriptor upload: %s", hipGetErrorString(e));
+  return DGBGK_OK;
+}
+
+int launch_class(dgbgk_batch *b, const dgbgk_batch::Class &c, int stage) {
+  const size_t nm = c.members.size();
+  const void *descs = b->dev + c.off_desc + (size_t)stage * nm * c.desc_size;
+  const int2 *items = (const int2 *)(b->dev + c.off_items);
+  hipError_t e;
+  if (is_fp32(c.prec))
+    e = launch_batch_stage32(c.p, stage, c.cw, c.contract, (const Stage32Args *)descs, items,
+                             (int)c.items.size(), c.lds, c.groups, b->stream);
+  else
+    e = launch_batch_stage(c.p, stage, (const StageArgs *)descs, items, (int)c.items.size(), c.lds,
+                           c.groups, b->stream);
+  if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "batched stage kernel: %s", hipGetErrorString(e));
+  return DGBGK_OK;
+}
+
+int enqueue_step(dgbgk_batch *b) {
+  for (int stage = 1; stage <= 4; ++stage)
+    for (const auto &c : b->cls) {
+      int rc = launch_class(b, c, stage);
+      if (rc) return rc;
+    }
+  return DGBGK_OK;
+}
+
+void drop_graph(dgbgk_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream,
+                       dgbgk_batch **out) {
+  if (!out) return bfail(nullptr, DGBGK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!solvers || n < 1) return bfail(nullptr, DGBGK_EINVAL, "need at least one solver");
+  for (int i = 0; i < n; ++i) {
+    if (!solvers[i]) return bfail(nullptr, DGBGK_EINVAL, "solver %d is NULL", i);
+    for (int j = 0; j < i; ++j)
+      if (solvers[j] == solvers[i]) return bfail(nullptr, DGBGK_EINVAL, "solver %d appears twice", i);
+  }
+  dgbgk_batch *b = new (std::nothrow) dgbgk_batch;
+  if (!b) return bfail(nullptr, DGBGK_ENOMEM, "out of host memory");
+  b->s.assign(solvers, solvers + n);
+  b->stream = (hipStream_t)hip_stream;
+  int rc = DGBGK_OK;
+  for (int i = 0; i < n && !rc; ++i) {
+    dgbgk_solver *s = b->s[i];
+    if (!s->fused || s->persistent) {  // members run the fused per-block body
+      s->tiling_mode = 1;
+      choose_tiling(s);
+    }
+    if (!s->fused || !tiling_admissible(s))
+      rc = bfail(nullptr, DGBGK_ENOTSUP, "solver %d: its fused tile does not fit in LDS", i);
+    else if ((rc = ensure_device(s)))
+      bfail(nullptr, rc, "solver %d: %s", i, s->err.c_str());
+  }
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  // classes of (precision, p, access width, contraction, LDS bin)
+  const size_t bins[4] = {40 * 1024, 64 * 1024, 80 * 1024, 160 * 1024};
+  for (int i = 0; i < n; ++i) {
+    dgbgk_solver *s = b->s[i];
+    const bool f32 = is_fp32(s->prec);
+    const int cw = f32 ? (((int64_t)s->Q * s->Np) % 4 == 0 ? 4 : 1) : 0;
+    const int contract = s->prec == DGBGK_FP32_BF16MMA;
+    int bin = 0;
+    while (bin < 3 && s->lds > bins[bin]) ++bin;
+    const int prec_class = f32 ? DGBGK_FP32 : DGBGK_FP64;
+    size_t k = 0;
+    for (; k < b->cls.size(); ++k) {
+      const auto &c = b->cls[k];
+      if (c.prec == prec_class && c.p == s->p && c.cw == cw && c.contract == contract &&
+          c.lds_bin == bin)
+        break;
+    }
+    if (k == b->cls.size()) {
+      dgbgk_batch::Class c;
+      c.prec = prec_class;
+      c.p = s->p;
+      c.cw = cw;
+      c.contract = contract;
+      c.lds_bin = bin;
+      b->cls.push_back(c);
+    }
+    auto &c = b->cls[k];
+    const int li = (int)c.members.size();
+    c.members.push_back(i);
+    for (int blk = 0; blk < s->nblk; ++blk) c.items.push_back(make_int2(li, blk));
+    c.lds = std::max(c.lds, s->lds);
+  }
+  // device layout: per class its items, then its descriptors (5 stages x members)
+  size_t off = 0;
+  for (auto &c : b->cls) {
+    // the kernels index the table as an array of the argument struct: the
+    // stride must be exactly its size
+    c.desc_size = is_fp32(c.prec) ? sizeof(Stage32Args) : sizeof(StageArgs);
+    c.off_items = off;
+    off += round_up(c.items.size() * sizeof(int2));
+    c.off_desc = off;
+    off += round_up(5 * c.members.size() * c.desc_size);
+    const int per_cu = std::max(1, std::min(is_fp32(c.prec) ? 3 : 2, (int)((160 * 1024) / c.lds)));
+    c.groups = (int)std::min<size_t>(c.items.size(), (size_t)per_cu * b->s[c.members[0]]->num_cu);
+  }
+  b->host.assign(off, 0);
+  for (auto &c : b->cls)
+    std::memcpy(b->host.data() + c.off_items, c.items.data(), c.items.size() * sizeof(int2));
+  hipError_t e = hipMalloc((void **)&b->dev, off);
+  if (e != hipSuccess) {
+    delete b;
+    return bfail(nullptr, DGBGK_ENOMEM, "hipMalloc(%zu): %s", off, hipGetErrorString(e));
+  }
+  if (!b->stream) {
+    // a stream of its own (ordered with the null stream), needed for graph capture
+    e = hipStreamCreate(&b->stream);
+    if (e != hipSuccess) {
+      (void)hipFree(b->dev);
+      delete b;
+      return bfail(nullptr, DGBGK_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    b->own_stream = true;
+  }
+  b->dt_loaded.assign(n, std::nan(""));
+  fill_descriptors(b, nullptr);
+  if ((rc = upload_descriptors(b))) {
+    const std::string msg = b->err;
+    dgbgk_batch_destroy(b);
+    return bfail(nullptr, rc, "%s", msg.c_str());
+  }
+  *out = b;
+  return DGBGK_OK;
+}
+
+int dgbgk_batch_set_graph(dgbgk_batch *b, int32_t use_graph) {
+  if (!b) return bfail(nullptr, DGBGK_EINVAL, "batch is NULL");
+  b->use_graph = use_graph != 0;
+  if (!b->use_graph) drop_graph(b);
+  return DGBGK_OK;
+}
+
+int dgbgk_batch_step(dgbgk_batch *b, int64_t nsteps, const double *dt) {
+  if (!b) return bfail(nullptr, DGBGK_EINVAL, "batch is NULL");
+  if (nsteps < 0 || !dt) return bfail(b, DGBGK_EINVAL, "need nsteps >= 0 and dt");
+  const size_t n = b->s.size();
+  for (size_t i = 0; i < n; ++i) {
+    if (!(dt[i] > 0) || !std::isfinite(dt[i])) return bfail(b, DGBGK_EINVAL, "dt[%zu] must be > 0", i);
+    if (!b->s[i]->have_state) return bfail(b, DGBGK_ESTATE, "member %zu has no state", i);
+  }
+  bool changed = false;
+  for (size_t i = 0; i < n; ++i) changed |= !(b->dt_loaded[i] == dt[i]);
+  int rc;
+  if (changed) {
+    // the stream may still run replays that read the tables: wait before rewriting them
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "synchronize: %s", hipGetErrorString(e));
+    fill_descriptors(b, dt);
+    if ((rc = upload_descriptors(b))) return rc;
+    for (size_t i = 0; i < n; ++i) b->dt_loaded[i] = dt[i];
+  }
+  if (nsteps == 0) return DGBGK_OK;
+  if (b->use_graph && !b->exec) {
+    // one eager step sets the kernels' LDS attributes before the capture
+    if ((rc = enqueue_step(b))) return rc;
+    --nsteps;
+    for (auto *s : b->s) ++s->steps;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "begin capture: %s", hipGetErrorString(e));
+    rc = enqueue_step(b);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    b->graph = g;
+    if (e != hipSuccess) {
+      drop_graph(b);
+      return bfail(b, DGBGK_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    }
+  }
+  for (int64_t it = 0; it < nsteps; ++it) {
+    if (b->use_graph) {
+      hipError_t e = hipGraphLaunch(b->exec, b->stream);
+      if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+    } else if ((rc = enqueue_step(b))) {
+      return rc;
+    }
+  }
+  for (auto *s : b->s) s->steps += nsteps;
+  return DGBGK_OK;
+}
+
+int dgbgk_batch_residuals(dgbgk_batch *b, double *r) {
+  if (!b) return bfail(nullptr, DGBGK_EINVAL, "batch is NULL");
+  if (!r) return bfail(b, DGBGK_EINVAL, "r is NULL");
+  const size_t n = b->s.size();
+  std::vector<unsigned long long> bits(n, 0ull);
+  for (size_t i = 0; i < n; ++i) {
+    dgbgk_solver *s = b->s[i];
+    if (!s->have_state) return bfail(b, DGBGK_ESTATE, "member %zu has no state", i);
+    hipStream_t saved = s->stream;
+    s->stream = b->stream;
+    int rc = residual_enqueue(s);
+    hipError_t e = hipSuccess;
+    if (!rc)
+      e = hipMemcpyAsync(&bits[i], s->d_u64, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         b->stream);
+    s->stream = saved;
+    if (rc) return bfail(b, rc, "member %zu: %s", i, s->err.c_str());
+    if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "residual copy: %s", hipGetErrorString(e));
+  }
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "synchronize: %s", hipGetErrorString(e));
+  int rc = DGBGK_OK;
+  for (size_t i = 0; i < n; ++i) {
+    double v;
+    std::memcpy(&v, &bits[i], sizeof v);
+    if (!std::isfinite(v)) {
+      v = NAN;
+      rc = bfail(b, DGBGK_ENONFINITE, "member %zu: residual is not finite", i);
+    }
+    r[i] = v;
+  }
+  return rc;
+}
+
+int dgbgk_batch_launches_per_step(const dgbgk_batch *b, int32_t *launches) {
+  if (!b) return bfail(nullptr, DGBGK_EINVAL, "batch is NULL");
+  if (!launches) return bfail(const_cast<dgbgk_batch *>(b), DGBGK_EINVAL, "launches is NULL");
+  *launches = (int32_t)(4 * b->cls.size());
+  return DGBGK_OK;
+}
+
+const char *dgbgk_batch_last_error(const dgbgk_batch *b) {
+  if (!b) return g_create_error.c_str();
+  return b->err.c_str();
+}
+
+void dgbgk_batch_destroy(dgbgk_batch *b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  if (b->dev) (void)hipFree(b->dev);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
 }
 
 }  // extern "C"

@@ -446,9 +446,10 @@ __device__ __forceinline__ void row_rhs(const StageArgs &a, double *row, const d
 }
 
 // MODE: 0 writes L(f_s); 1 first RK4 stage; 2 second and third; 4 fourth.
-// One work-group per (element block, velocity tile); the general kernel.
+// One element block blk and velocity tile tile_y of the stage, by one
+// work-group; the body of the general kernel and of the batched kernel.
 template <int P, int MODE>
-__global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
+__device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int tile_y) {
   using Sh = Shape<P>;
   constexpr int NP = Sh::NP, NFP = Sh::NFP, S = Sh::S;
   constexpr int CW = Sh::VEC ? 2 : 1;  // doubles per global access
@@ -466,10 +467,9 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
 
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
-  const int blk = xcd_block(blockIdx.x, a.nblk);
   const int k0 = blk * E;
   const int Eb = min(E, a.K - k0);
-  const int q0 = blockIdx.y * a.Qt;
+  const int q0 = tile_y * a.Qt;
   const int Qb = min(a.Qt, a.Q - q0);
   const int rows = Qb * E;  // LDS row r = q_local * E + e
   const int nch = rows * CPE;
@@ -586,6 +586,39 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
       *reinterpret_cast<V *>(outr + go[u]) = o;
       if (MODE == 1 || MODE == 2) *reinterpret_cast<V *>(accr + go[u]) = an;
     }
+  }
+}
+
+// One work-group per (element block, velocity tile); the general kernel.
+template <int P, int MODE>
+__global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
+  stage_block<P, MODE>(a, xcd_block(blockIdx.x, a.nblk), blockIdx.y);
+}
+
+// Batched stage over several problems of the same order P: work item i is
+// (problem, element block); work-groups stride over the items.  The
+// per-problem arguments are read from a descriptor table in the constant
+// address space (scalar loads), written before the launch and unchanged
+// during it.  Fused blocks only (all velocities of a block per work-group).
+typedef __attribute__((address_space(4))) const StageArgs ConstStageArgs;
+
+template <int P, int MODE>
+__global__ __launch_bounds__(kBlock) void batch_stage_kernel(const StageArgs *descs,
+                                                              const int2 *items, int nitems) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  ConstStageArgs *cd = (ConstStageArgs *)descs;
+#endif
+  for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const int2 it = items[i];
+    const int inst = __builtin_amdgcn_readfirstlane(it.x);
+    const int blk = __builtin_amdgcn_readfirstlane(it.y);
+#if defined(__HIP_DEVICE_COMPILE__)
+    const StageArgs a = cd[inst];  // scalar loads from the constant address space
+#else
+    const StageArgs a = descs[inst];  // host pass: the body is never run on the host
+#endif
+    stage_block<P, MODE>(a, blk, 0);
+    __syncthreads();  // LDS is reused by the next item
   }
 }
 
@@ -937,6 +970,32 @@ hipError_t launch_stream_p(const StageArgs &a, size_t lds, int groups, hipStream
   }
 }
 
+template <int P, int MODE>
+hipError_t launch_batch_pm(const StageArgs *descs, const int2 *items, int nitems, size_t lds,
+                           int groups, hipStream_t st) {
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void *)batch_stage_kernel<P, MODE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((batch_stage_kernel<P, MODE>), dim3((unsigned)groups), dim3(kBlock), lds, st,
+                     descs, items, nitems);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_batch_p(int stage, const StageArgs *descs, const int2 *items, int nitems,
+                          size_t lds, int groups, hipStream_t st) {
+  switch (stage) {
+    case 0: return launch_batch_pm<P, 0>(descs, items, nitems, lds, groups, st);
+    case 1: return launch_batch_pm<P, 1>(descs, items, nitems, lds, groups, st);
+    case 2:
+    case 3: return launch_batch_pm<P, 2>(descs, items, nitems, lds, groups, st);
+    case 4: return launch_batch_pm<P, 4>(descs, items, nitems, lds, groups, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int P>
 hipError_t launch_stage_p(const StageArgs &a, size_t lds, int ntiles, hipStream_t st) {
   switch (a.stage) {
@@ -977,6 +1036,22 @@ hipError_t launch_stream(int p, const StageArgs &a, size_t lds, int groups, hipS
     case 1: return launch_stream_p<1>(a, lds, groups, st);
     case 2: return launch_stream_p<2>(a, lds, groups, st);
     case 3: return launch_stream_p<3>(a, lds, groups, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_batch_stage(int p, int stage, const StageArgs *descs, const int2 *items,
+                              int nitems, size_t lds, int groups, hipStream_t st) {
+  if (nitems <= 0 || groups <= 0) return hipSuccess;
+  switch (p) {
+    case 1: return launch_batch_p<1>(stage, descs, items, nitems, lds, groups, st);
+    case 2: return launch_batch_p<2>(stage, descs, items, nitems, lds, groups, st);
+    case 3: return launch_batch_p<3>(stage, descs, items, nitems, lds, groups, st);
+    case 4: return launch_batch_p<4>(stage, descs, items, nitems, lds, groups, st);
+    case 5: return launch_batch_p<5>(stage, descs, items, nitems, lds, groups, st);
+    case 6: return launch_batch_p<6>(stage, descs, items, nitems, lds, groups, st);
+    case 7: return launch_batch_p<7>(stage, descs, items, nitems, lds, groups, st);
+    case 8: return launch_batch_p<8>(stage, descs, items, nitems, lds, groups, st);
     default: return hipErrorInvalidValue;
   }
 }

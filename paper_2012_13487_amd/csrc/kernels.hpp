@@ -55,6 +55,13 @@ size_t stage_lds_bytes(int p, int E, int Qt);
 hipError_t launch_stage(int p, const StageArgs &a, size_t lds_bytes, int ntiles,
                         hipStream_t stream);
 
+// Batched stage: problems of order p (fused blocks), one work item per
+// (problem, element block) in items (.x problem index into descs, .y block);
+// groups work-groups stride over the items.  descs (device) must hold the
+// stage's arguments of every problem for the duration of the launch.
+hipError_t launch_batch_stage(int p, int stage, const StageArgs *descs, const int2 *items,
+                              int nitems, size_t lds_bytes, int groups, hipStream_t stream);
+
 // The persistent pipelined stage kernel applies to fused blocks with at most
 // kBlock velocity rows (E * Q) and at most kStreamDoubles * kBlock f values,
 // p <= kStreamMaxP, and f arrays below 4 GiB (32-bit offsets).

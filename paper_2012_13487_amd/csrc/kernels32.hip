@@ -152,7 +152,7 @@ __device__ __forceinline__ void volume_bf16(const float *tile, int S, int r0w, i
 // CW: floats per global access (4 when Q Np is a multiple of 4, else 1).
 // BF: the volume term's contractions Dr g, Ds g on bf16 matrix cores.
 template <int P, int MODE, int CW, bool BF>
-__global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) {
+__device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
   using Sh = Shape32<P>;
   constexpr int N1 = Sh::N1, NP = Sh::NP, NFP = Sh::NFP, S = Sh::S, NB = Sh::NB;
   constexpr int U = 8;  // global accesses in flight per thread
@@ -167,7 +167,6 @@ __global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) 
   int *nbr = (int *)(lds + L.nbr);
 
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int blk = xcd_block32(blockIdx.x, a.nblk);
   const int k0 = blk * E;
   const int Eb = min(E, a.K - k0);
   const int QNP = Q * NP;
@@ -447,6 +446,36 @@ __global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) 
   }
 }
 
+template <int P, int MODE, int CW, bool BF>
+__global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) {
+  stage32_block<P, MODE, CW, BF>(a, xcd_block32(blockIdx.x, a.nblk));
+}
+
+// Batched FP32 stage over problems of the same order P and access width CW:
+// work item i is (problem, element block); the per-problem arguments come from
+// a descriptor table in the constant address space (see batch_stage_kernel).
+typedef __attribute__((address_space(4))) const Stage32Args ConstStage32Args;
+
+template <int P, int MODE, int CW, bool BF>
+__global__ __launch_bounds__(kBlock32) void batch_stage32_kernel(const Stage32Args *descs,
+                                                                  const int2 *items, int nitems) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  ConstStage32Args *cd = (ConstStage32Args *)descs;
+#endif
+  for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const int2 it = items[i];
+    const int inst = __builtin_amdgcn_readfirstlane(it.x);
+    const int blk = __builtin_amdgcn_readfirstlane(it.y);
+#if defined(__HIP_DEVICE_COMPILE__)
+    const Stage32Args a = cd[inst];  // scalar loads from the constant address space
+#else
+    const Stage32Args a = descs[inst];  // host pass: the body is never run on the host
+#endif
+    stage32_block<P, MODE, CW, BF>(a, blk);
+    __syncthreads();  // LDS is reused by the next item
+  }
+}
+
 __global__ void to_dev32_kernel(const double *src, float *dst, const double *vel, size_t KNP, int Np,
                                 int Q, double offset) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // k * Np + n
@@ -527,6 +556,39 @@ __global__ __launch_bounds__(256) void residual32_kernel(const float *k, const d
 }
 
 template <int P, int MODE, int CW, bool BF>
+hipError_t launch_batch32_pmcb(const Stage32Args *descs, const int2 *items, int nitems, size_t lds,
+                               int groups, hipStream_t st) {
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void *)batch_stage32_kernel<P, MODE, CW, BF>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((batch_stage32_kernel<P, MODE, CW, BF>), dim3((unsigned)groups), dim3(kBlock32),
+                     lds, st, descs, items, nitems);
+  return hipGetLastError();
+}
+
+template <int P, int CW, bool BF>
+hipError_t launch_batch32_pcb(int stage, const Stage32Args *descs, const int2 *items, int nitems,
+                              size_t lds, int groups, hipStream_t st) {
+  switch (stage) {
+    case 0: return launch_batch32_pmcb<P, 0, CW, BF>(descs, items, nitems, lds, groups, st);
+    case 1: return launch_batch32_pmcb<P, 1, CW, BF>(descs, items, nitems, lds, groups, st);
+    case 2:
+    case 3: return launch_batch32_pmcb<P, 2, CW, BF>(descs, items, nitems, lds, groups, st);
+    case 4: return launch_batch32_pmcb<P, 4, CW, BF>(descs, items, nitems, lds, groups, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int P, bool BF>
+hipError_t launch_batch32_pb(int stage, int cw, const Stage32Args *descs, const int2 *items,
+                             int nitems, size_t lds, int groups, hipStream_t st) {
+  if (cw == 4) return launch_batch32_pcb<P, 4, BF>(stage, descs, items, nitems, lds, groups, st);
+  return launch_batch32_pcb<P, 1, BF>(stage, descs, items, nitems, lds, groups, st);
+}
+
+template <int P, int MODE, int CW, bool BF>
 hipError_t launch32_pmcb(const Stage32Args &a, size_t lds, hipStream_t st) {
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void *)stage32_kernel<P, MODE, CW, BF>,
@@ -579,6 +641,32 @@ size_t stage32_lds_bytes(int p, int E, int Q, bool bf16) {
 }
 
 bool bf16_contraction_available(int p) { return p >= 1 && p <= 4; }
+
+hipError_t launch_batch_stage32(int p, int stage, int cw, int contract, const Stage32Args *descs,
+                                const int2 *items, int nitems, size_t lds, int groups,
+                                hipStream_t st) {
+  if (nitems <= 0 || groups <= 0) return hipSuccess;
+  if (contract) {
+    switch (p) {
+      case 1: return launch_batch32_pb<1, true>(stage, cw, descs, items, nitems, lds, groups, st);
+      case 2: return launch_batch32_pb<2, true>(stage, cw, descs, items, nitems, lds, groups, st);
+      case 3: return launch_batch32_pb<3, true>(stage, cw, descs, items, nitems, lds, groups, st);
+      case 4: return launch_batch32_pb<4, true>(stage, cw, descs, items, nitems, lds, groups, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (p) {
+    case 1: return launch_batch32_pb<1, false>(stage, cw, descs, items, nitems, lds, groups, st);
+    case 2: return launch_batch32_pb<2, false>(stage, cw, descs, items, nitems, lds, groups, st);
+    case 3: return launch_batch32_pb<3, false>(stage, cw, descs, items, nitems, lds, groups, st);
+    case 4: return launch_batch32_pb<4, false>(stage, cw, descs, items, nitems, lds, groups, st);
+    case 5: return launch_batch32_pb<5, false>(stage, cw, descs, items, nitems, lds, groups, st);
+    case 6: return launch_batch32_pb<6, false>(stage, cw, descs, items, nitems, lds, groups, st);
+    case 7: return launch_batch32_pb<7, false>(stage, cw, descs, items, nitems, lds, groups, st);
+    case 8: return launch_batch32_pb<8, false>(stage, cw, descs, items, nitems, lds, groups, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_stage32(int p, const Stage32Args &a, size_t lds, int contract, hipStream_t st) {
   if (!contract) return launch32_b<false>(p, a, lds, st);

@@ -51,6 +51,13 @@ size_t stage32_lds_bytes(int p, int E, int Q, bool bf16);
 hipError_t launch_stage32(int p, const Stage32Args &a, size_t lds_bytes, int contract,
                           hipStream_t stream);
 
+// Batched FP32 stage over problems of order p with the same access width cw
+// (4 when Q Np is a multiple of 4, else 1) and contraction variant; items and
+// descs as for launch_batch_stage.
+hipError_t launch_batch_stage32(int p, int stage, int cw, int contract, const Stage32Args *descs,
+                                const int2 *items, int nitems, size_t lds_bytes, int groups,
+                                hipStream_t stream);
+
 // f (double, host order f[q][k][n]) <-> g (float, element-major), with
 // g = f - offset * w_q (offset = rho_ref for states, 0 for rates).
 hipError_t launch_to_dev32(const double *src, float *dst, const double *vel, int K, int Np, int Q,

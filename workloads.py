@@ -75,6 +75,33 @@ CAVITY_64x64_P3_NC16 = cavity(n=64, p=3, m=16, kn=1.0)           # FP64
 CAVITY_128x128_P4_NC24_KN8 = cavity(n=128, p=4, m=24, kn=8.0)    # precision path
 
 
+def batch_instances(seed=0, n=64, n_range=(16, 96), p_choices=(2, 3, 4), kn_log10=(-1.0, 1.0),
+                    m_range=(8, 24), steps=1000):
+    """The mixed batch: n seeded problems, each a Couette or a cavity flow
+    (equal odds) on an N x N mesh with N uniform in n_range, p uniform in
+    p_choices, Kn log-uniform over 10**kn_log10, and the velocity set D2Q16
+    Gauss-Hermite or Newton-Cotes M x M with M uniform in m_range (equal odds).
+    Draws come from numpy.random.default_rng(seed) in a fixed order per
+    problem (flow, N, p, Kn, set kind, M)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        flow = "couette" if rng.integers(2) == 0 else "cavity"
+        N = int(rng.integers(n_range[0], n_range[1] + 1))
+        p = int(p_choices[rng.integers(len(p_choices))])
+        kn = float(10.0 ** rng.uniform(*kn_log10))
+        gh = rng.integers(2) == 0
+        M = int(rng.integers(m_range[0], m_range[1] + 1))
+        velset = ("gh", 4) if gh else ("nc", M, 4.0)
+        if flow == "couette":
+            spec = couette(nx=N, ny=N, p=p, kn=kn, velset=velset, steps=steps)
+        else:
+            spec = cavity(n=N, p=p, m=M, kn=kn, steps=steps).with_(velset=velset)
+        vs = "gh4" if gh else f"nc{M}"
+        out.append(spec.with_(name=f"b{i:02d}_{flow}_{N}x{N}_p{p}_{vs}_kn{kn:.3g}"))
+    return out
+
+
 def uniform_noise(seed, shape, lo=-1.0, hi=1.0):
     """Seeded uniform noise on [lo, hi)."""
     return np.random.default_rng(seed).uniform(lo, hi, size=shape)
