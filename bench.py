@@ -176,7 +176,7 @@ def batching(steps):
         res = {"value": dof * 4 * steps / (ms / 1000.0), "unit": "DOF-updates/s",
                "ms_per_step": ms / steps, "launches_per_step": launches}
         if tuned:
-            res["autotuned_elems_per_group"] = {f"p{p}_Q{q}": e for (p, q), e in sorted(tuned.items())}
+            res["autotuned_classes"] = len(tuned)
         return res, dof
 
     out["sequential_fp64"], out["dof"] = run("fp64", False)
@@ -186,6 +186,40 @@ def batching(steps):
                                            / out["sequential_fp64"]["value"])
     out["batched_fp32_over_sequential_fp64"] = (out["batched_fp32_graph"]["value"]
                                                 / out["sequential_fp64"]["value"])
+    return out
+
+
+def serving(n_requests, n_range=(16, 28)):
+    """Steady-state serving (continuous batching) of a seeded Poisson stream
+    (rate 20/s, seed 1) of requests drawn from the mixed-problem distribution
+    scaled to small meshes (seed 2), each run from rest to residual 1e-6:
+    served DOF-updates/s and p50/p99 latency (arrival to residual 1e-6), plain
+    FP64 against FP32 storage finished in FP64."""
+    import workloads
+    from paper_2012_13487_amd import Server
+
+    reqs = workloads.batch_instances(seed=2, n=n_requests, n_range=n_range, p_choices=(2, 3),
+                                     kn_log10=(-0.5, 1.0), m_range=(6, 12))
+    arrivals = workloads.poisson_arrivals(seed=1, rate=20.0, n=n_requests)
+    out = {"workload": f"{n_requests} requests, Poisson arrivals at 20/s (seed 1), problems "
+                       f"from the mixed distribution on N x N quads with N in {n_range[0]}.."
+                       f"{n_range[1]}, p in 2..3, "
+                       "Kn log-uniform in [0.3, 10], D2Q16 GH or NC MxM with M in 6..12 (seed 2)",
+           "residual_target": 1e-6, "check_every": 50}
+    for prec in ("fp64", "fp32"):
+        sv = Server(hbm_budget=16 << 30, max_active=64, precision=prec, residual_target=1e-6,
+                    check_every=50, max_steps=2_000_000, graph=True)
+        ids = [sv.submit(r, a) for r, a in zip(reqs, arrivals)]
+        sv.run(600.0)
+        st = sv.stats()
+        conv = sum(sv.result(i)["status"] == 2 for i in ids)
+        sv.close()
+        out["fp64" if prec == "fp64" else "fp32_then_fp64"] = {
+            "value": st["dof_updates"] / st["wall_s"], "unit": "DOF-updates/s",
+            "latency_p50_s": st["latency_p50_s"], "latency_p99_s": st["latency_p99_s"],
+            "wall_s": st["wall_s"], "converged": conv, "peak_active": st["peak_active"],
+            "batch_rebuilds": st["batch_rebuilds"], "precision_switches": st["precision_switches"]}
+    out["mixed_over_fp64"] = out["fp32_then_fp64"]["value"] / out["fp64"]["value"]
     return out
 
 
@@ -213,6 +247,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-path", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB (5 times), to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters of the stage kernel")
@@ -316,6 +351,8 @@ def main():
         out["precision_path"] = precision_path(100, 20)
     if not args.no_batching:
         out["batching"] = batching(10)
+    if not args.no_serving:
+        out["serving"] = serving(32)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_budget)
     print(json.dumps(out), flush=True)

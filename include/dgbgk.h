@@ -285,6 +285,86 @@ int dgbgk_batch_launches_per_step(const dgbgk_batch *b, int32_t *launches);
 const char *dgbgk_batch_last_error(const dgbgk_batch *b);
 void dgbgk_batch_destroy(dgbgk_batch *b);
 
+/* ---- serving: steady-state solves under continuous batching --------------
+ *
+ * A server takes requests (a problem and an arrival time on the server's
+ * clock, in seconds from the start of dgbgk_server_run) and runs each from
+ * rest (f = f^eq(1, 0)) to the steady-state residual target (dgbgk_residual
+ * below residual_target), keeping its state on the device the whole time.
+ * Arrived requests are admitted first come, first served while the device
+ * memory they need (dgbgk_required_bytes) fits in hbm_budget and fewer than
+ * max_active are running; admitted problems are advanced together as one
+ * batch (dgbgk_batch_*) in chunks of check_every RK4 steps, with the batch
+ * rebuilt whenever a request joins or leaves, so requests that arrive while
+ * others run share the device with them.  Residuals are checked, and requests
+ * join and leave, only at chunk boundaries of each request's own step count,
+ * so every result is bit-identical to the same request served alone.  A
+ * finished request's node moments are copied to host memory and its device
+ * memory is released.  dt = the problem's stable step at cfl.
+ *
+ * Mixed precision: with precision DGBGK_FP32 (or DGBGK_FP32_BF16MMA) and
+ * polish_below > 0, a request runs in that precision until its residual falls
+ * below polish_below or stops falling (less than 10% lower than its best over
+ * 20 checks), then its state moves to an FP64 solver that finishes the solve
+ * (FP32 storage cannot reach residuals much below 1e-5: its rounding floor).
+ * The device memory of such a request is reserved at the FP64 size. */
+typedef struct dgbgk_server dgbgk_server;
+
+typedef struct {
+  size_t hbm_budget;        /* bytes of device memory for admitted problems (> 0)   */
+  int32_t max_active;       /* problems on the device at once (>= 1)                */
+  int32_t precision;        /* dgbgk_precision of every request                     */
+  double residual_target;   /* e.g. 1e-6 (> 0)                                      */
+  int32_t check_every;      /* RK4 steps between residual checks (>= 1)             */
+  int64_t max_steps;        /* per-request cap: stopped unconverged beyond it (>= 1) */
+  double cfl;               /* dt = dgbgk_stable_dt(cfl) (> 0)                      */
+  int32_t use_graph;        /* replay each batch step from a hipGraph               */
+  double polish_below;      /* FP32 precisions: switch to FP64 below this residual  */
+} dgbgk_server_options;
+
+typedef enum {
+  DGBGK_REQ_WAITING = 0,    /* not yet arrived or not yet admitted      */
+  DGBGK_REQ_RUNNING = 1,
+  DGBGK_REQ_CONVERGED = 2,  /* residual below the target                */
+  DGBGK_REQ_STOPPED = 3,    /* max_steps reached first                  */
+  DGBGK_REQ_FAILED = 4      /* non-finite state or an error (see stats) */
+} dgbgk_request_status;
+
+typedef struct {
+  int32_t status;           /* dgbgk_request_status                     */
+  double arrival_s, admit_s, finish_s;  /* server clock, seconds        */
+  int64_t steps;            /* RK4 steps taken                          */
+  double residual;          /* last residual                            */
+  int64_t dof;              /* Q K Np                                   */
+  int64_t K, Np;            /* sizes of the moment arrays (K*Np each)   */
+  int64_t steps_fp64;       /* of which in FP64 after a precision switch */
+} dgbgk_request_result;
+
+typedef struct {
+  int64_t submitted, completed;  /* completed = converged + stopped + failed */
+  double wall_s;                 /* duration of dgbgk_server_run                */
+  double dof_updates;            /* sum over requests of dof x 4 x steps        */
+  double latency_p50_s, latency_p99_s;  /* finish - arrival over completed      */
+  int64_t batch_rebuilds, chunks;
+  int32_t peak_active;
+  size_t peak_bytes;
+  int64_t precision_switches;    /* requests moved from FP32 to FP64 */
+} dgbgk_server_stats;
+
+int dgbgk_server_create(const dgbgk_server_options *opt, void *hip_stream, dgbgk_server **out);
+/* Copies the problem; *id is its index (0, 1, ...). */
+int dgbgk_server_submit(dgbgk_server *sv, const dgbgk_problem *pb, double arrival_s, int64_t *id);
+/* Runs until every submitted request has completed, or time_limit_s of wall
+ * time have passed (then DGBGK_ESTATE; running requests stay running and a
+ * later call resumes, with the clock continuing). */
+int dgbgk_server_run(dgbgk_server *sv, double time_limit_s);
+int dgbgk_server_result(const dgbgk_server *sv, int64_t id, dgbgk_request_result *out);
+/* Node moments of a completed request (host arrays of K*Np). */
+int dgbgk_server_moments(const dgbgk_server *sv, int64_t id, double *rho, double *ux, double *uy);
+int dgbgk_server_get_stats(const dgbgk_server *sv, dgbgk_server_stats *out);
+const char *dgbgk_server_last_error(const dgbgk_server *sv);
+void dgbgk_server_destroy(dgbgk_server *sv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,6 +38,30 @@ class Problem(C.Structure):
     ]
 
 
+class ServerOptions(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int32), ("precision", C.c_int32),
+                ("residual_target", C.c_double), ("check_every", C.c_int32),
+                ("max_steps", C.c_int64), ("cfl", C.c_double), ("use_graph", C.c_int32),
+                ("polish_below", C.c_double)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("arrival_s", C.c_double), ("admit_s", C.c_double),
+                ("finish_s", C.c_double), ("steps", C.c_int64), ("residual", C.c_double),
+                ("dof", C.c_int64), ("K", C.c_int64), ("Np", C.c_int64),
+                ("steps_fp64", C.c_int64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("wall_s", C.c_double),
+                ("dof_updates", C.c_double), ("latency_p50_s", C.c_double),
+                ("latency_p99_s", C.c_double), ("batch_rebuilds", C.c_int64),
+                ("chunks", C.c_int64), ("peak_active", C.c_int32), ("peak_bytes", C.c_size_t),
+                ("precision_switches", C.c_int64)]
+
+
+REQ_WAITING, REQ_RUNNING, REQ_CONVERGED, REQ_STOPPED, REQ_FAILED = 0, 1, 2, 3, 4
+
 # name -> (restype, argtypes) for every function declared in include/dgbgk.h
 SIGNATURES = {
     "dgbgk_velset_gh": (C.c_int, [C.c_int32, _dp, _dp, _dp, _dp]),
@@ -80,6 +104,15 @@ SIGNATURES = {
     "dgbgk_batch_launches_per_step": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "dgbgk_batch_last_error": (C.c_char_p, [C.c_void_p]),
     "dgbgk_batch_destroy": (None, [C.c_void_p]),
+    "dgbgk_server_create": (C.c_int, [C.POINTER(ServerOptions), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "dgbgk_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Problem), C.c_double,
+                                      C.POINTER(C.c_int64)]),
+    "dgbgk_server_run": (C.c_int, [C.c_void_p, C.c_double]),
+    "dgbgk_server_result": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(RequestResult)]),
+    "dgbgk_server_moments": (C.c_int, [C.c_void_p, C.c_int64, _dp, _dp, _dp]),
+    "dgbgk_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(ServerStats)]),
+    "dgbgk_server_last_error": (C.c_char_p, [C.c_void_p]),
+    "dgbgk_server_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None
@@ -385,6 +418,76 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             lib().dgbgk_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Steady-state solves under continuous batching (dgbgk_server_*): submit
+    problems with arrival times, run, then read per-request results and
+    latency / throughput statistics."""
+
+    def __init__(self, hbm_budget, max_active=64, precision=FP64, residual_target=1e-6,
+                 check_every=50, max_steps=10 ** 6, cfl=0.2, graph=True, stream=None,
+                 polish_below=None):
+        if stream == "torch":
+            import torch  # plumbing only: the stream
+            stream = torch.cuda.current_stream().cuda_stream
+        if polish_below is None:  # FP32 precisions: finish in FP64 below 30 x the target
+            polish_below = 0.0 if _prec(precision) == FP64 else 30.0 * residual_target
+        opt = ServerOptions(int(hbm_budget), int(max_active), _prec(precision),
+                            float(residual_target), int(check_every), int(max_steps), float(cfl),
+                            int(bool(graph)), float(polish_below))
+        h = C.c_void_p()
+        rc = lib().dgbgk_server_create(C.byref(opt), C.c_void_p(stream or 0), C.byref(h))
+        if rc != OK:
+            raise DgbgkError(rc, "invalid server options")
+        self._h = h.value
+        self._vel = []  # keeps submitted velocity arrays alive until submit copies them
+
+    def _check(self, rc):
+        if rc != OK:
+            raise DgbgkError(rc, lib().dgbgk_server_last_error(self._h).decode(errors="replace"))
+
+    def submit(self, spec, arrival_s):
+        vel = velocity_set(spec.velset)
+        tau = spec.tau if spec.tau is not None else tau_from_kn(spec.kn, spec.kn_length,
+                                                                spec.kn_convention)
+        pb = _problem(spec.nx, spec.ny, spec.p, vel, tau, spec.bc, spec.wall_u, spec.x0, spec.y0,
+                      spec.lx, spec.ly)
+        rid = C.c_int64()
+        self._check(lib().dgbgk_server_submit(self._h, C.byref(pb), float(arrival_s),
+                                              C.byref(rid)))
+        return rid.value
+
+    def run(self, time_limit_s=600.0):
+        self._check(lib().dgbgk_server_run(self._h, float(time_limit_s)))
+
+    def result(self, rid):
+        r = RequestResult()
+        self._check(lib().dgbgk_server_result(self._h, int(rid), C.byref(r)))
+        return {f: getattr(r, f) for f, _ in RequestResult._fields_}
+
+    def moments(self, rid):
+        r = self.result(rid)
+        n = r["K"] * r["Np"]
+        rho, ux, uy = np.zeros(n), np.zeros(n), np.zeros(n)
+        self._check(lib().dgbgk_server_moments(self._h, int(rid), _p(rho), _p(ux), _p(uy)))
+        return rho, ux, uy
+
+    def stats(self):
+        st = ServerStats()
+        self._check(lib().dgbgk_server_get_stats(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dgbgk_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -170,3 +170,56 @@ def test_device_calls_fail_loudly_without_gpu():
     with pytest.raises(binding.DgbgkError) as ei:
         s.step(1, 1e-3)
     assert ei.value.code == binding.ESTATE
+
+
+def test_server_validation_and_cpu_failure_path():
+    with pytest.raises(binding.DgbgkError):
+        binding.Server(hbm_budget=0)
+    with pytest.raises(binding.DgbgkError):
+        binding.Server(hbm_budget=1 << 30, check_every=0)
+    sv = binding.Server(hbm_budget=1 << 20, precision="fp32")
+    small = workloads.cavity(n=3, p=2, m=4)
+    rid = sv.submit(small, 0.0)
+    assert rid == 0
+    with pytest.raises(binding.DgbgkError) as ei:  # does not fit the budget
+        sv.submit(workloads.cavity(n=64, p=3, m=16), 0.0)
+    assert ei.value.code == binding.EINVAL
+    with pytest.raises(binding.DgbgkError) as ei:
+        sv.submit(small, -1.0)
+    assert ei.value.code == binding.EINVAL
+    with pytest.raises(binding.DgbgkError):
+        sv.result(5)
+    assert sv.result(0)["status"] == binding.REQ_WAITING
+    # without a GPU the admission fails loudly per request and the run ends
+    sv.run(5.0)
+    r = sv.result(0)
+    assert r["status"] == binding.REQ_FAILED
+    st = sv.stats()
+    assert st["submitted"] == 1 and st["completed"] == 1 and st["dof_updates"] == 0.0
+    with pytest.raises(binding.DgbgkError) as ei:
+        sv.moments(0)
+    assert ei.value.code == binding.ESTATE
+    sv.close()
+
+
+def test_batch_instances_and_arrivals_are_seeded():
+    a = workloads.batch_instances(seed=0, n=64)
+    b = workloads.batch_instances(seed=0, n=64)
+    assert [s.name for s in a] == [s.name for s in b] and len(a) == 64
+    assert {s.p for s in a} == {2, 3, 4}
+    assert all(16 <= s.nx <= 96 and s.nx == s.ny for s in a)
+    kns = np.array([s.kn for s in a])
+    assert kns.min() >= 0.1 and kns.max() <= 10.0
+    t = workloads.poisson_arrivals(seed=1, rate=20.0, n=2000)
+    assert np.all(np.diff(t) > 0)
+    assert abs(np.mean(np.diff(t)) - 0.05) < 0.005  # mean gap 1 / rate
+
+
+def test_batch_create_rejects_duplicates_without_device():
+    g = binding.Solver.from_spec(workloads.cavity(n=3, p=2, m=4))
+    with pytest.raises(binding.DgbgkError) as ei:
+        binding.Batch([g, g])
+    assert ei.value.code == binding.EINVAL
+    with pytest.raises(binding.DgbgkError) as ei:  # no GPU: device set-up fails loudly
+        binding.Batch([g])
+    assert ei.value.code == binding.EDEVICE

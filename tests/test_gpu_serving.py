@@ -1,0 +1,82 @@
+"""Serving on the GPU: steady-state solves under continuous batching.  Every
+request must end below the residual target, and its result must be the same
+alone and in the mix (bit for bit: each request's steps and checks depend only
+on its own residual history); the memory budget must bound the requests on
+the device; the mixed-precision server (FP32 storage, finished in FP64) must
+reach the same target."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from paper_2012_13487_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+REQS = workloads.batch_instances(seed=2, n=5, n_range=(5, 8), p_choices=(2, 3),
+                                 kn_log10=(0.0, 1.0), m_range=(6, 8))
+ARRIVALS = [0.0, 0.003, 0.006, 0.2, 0.21]
+
+
+def _serve(reqs, arrivals, **kw):
+    sv = binding.Server(hbm_budget=kw.pop("hbm_budget", 4 << 30), check_every=50,
+                        max_steps=300000, **kw)
+    ids = [sv.submit(r, a) for r, a in zip(reqs, arrivals)]
+    sv.run(240.0)
+    res = [sv.result(i) for i in ids]
+    mom = [sv.moments(i) for i in ids]
+    st = sv.stats()
+    sv.close()
+    return res, mom, st
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_served_alone_and_in_mix_identical(precision):
+    _say(f"[gpu] serving {precision}: mix of {len(REQS)} vs alone")
+    res, mom, st = _serve(REQS, ARRIVALS, precision=precision)
+    assert st["completed"] == len(REQS) and st["peak_active"] >= 2
+    for r in res:
+        assert r["status"] == binding.REQ_CONVERGED and r["residual"] < 1e-6
+    if precision == "fp32":
+        assert st["precision_switches"] >= 1
+    for i, req in enumerate(REQS):
+        ra, ma, _ = _serve([req], [0.0], precision=precision)
+        _say(f"  {req.name}: steps {res[i]['steps']} (fp64 {res[i]['steps_fp64']})")
+        assert ra[0]["steps"] == res[i]["steps"]
+        for a, b in zip(ma[0], mom[i]):
+            assert np.array_equal(a, b)
+
+
+def test_mixed_precision_reaches_the_fp64_steady_state():
+    # both end below residual 1e-6 in FP64 arithmetic, near the same steady state
+    _say("[gpu] serving fp32 + fp64 finish vs fp64")
+    r64, m64, _ = _serve(REQS, ARRIVALS, precision="fp64")
+    r32, m32, _ = _serve(REQS, ARRIVALS, precision="fp32")
+    for i in range(len(REQS)):
+        rho64, ux64, uy64 = m64[i]
+        rho32, ux32, uy32 = m32[i]
+        u64 = np.stack([ux64, uy64])
+        du = np.max(np.abs(np.stack([ux32, uy32]) - u64)) / np.max(np.abs(u64))
+        drho = np.max(np.abs(rho32 - rho64))
+        _say(f"  {REQS[i].name}: |du|/|u| {du:.2e}, |drho| {drho:.2e}")
+        assert du < 1e-3 and drho < 1e-4
+
+
+def test_admission_bounded_by_memory():
+    _say("[gpu] serving under a memory budget")
+    need = max(binding.required_bytes(r.nx, r.ny, r.p, binding.velocity_set(r.velset), 1.0,
+                                      r.bc, r.wall_u) for r in REQS)
+    res, mom, st = _serve(REQS, [0.0] * len(REQS), precision="fp64", hbm_budget=2 * need + 1)
+    assert st["peak_active"] <= 2 and st["peak_bytes"] <= 2 * need + 1
+    assert all(r["status"] == binding.REQ_CONVERGED for r in res)
+    ref, mref, _ = _serve(REQS, [0.0] * len(REQS), precision="fp64")
+    for a, b in zip(mom, mref):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)

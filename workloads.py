@@ -102,6 +102,12 @@ def batch_instances(seed=0, n=64, n_range=(16, 96), p_choices=(2, 3, 4), kn_log1
     return out
 
 
+def poisson_arrivals(seed=1, rate=20.0, n=64):
+    """Arrival times (seconds) of a Poisson stream of the given rate: the
+    cumulative sums of seeded exponential gaps."""
+    return np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, size=n))
+
+
 def uniform_noise(seed, shape, lo=-1.0, hi=1.0):
     """Seeded uniform noise on [lo, hi)."""
     return np.random.default_rng(seed).uniform(lo, hi, size=shape)
