@@ -438,8 +438,8 @@ class Server:
         if stream == "torch":
             import torch  # plumbing only: the stream
             stream = torch.cuda.current_stream().cuda_stream
-        if polish_below is None:  # FP32 precisions: finish in FP64 below 30 x the target
-            polish_below = 0.0 if _prec(precision) == FP64 else 30.0 * residual_target
+        if polish_below is None:  # FP32 precisions: finish in FP64 below 15 x the target
+            polish_below = 0.0 if _prec(precision) == FP64 else 15.0 * residual_target
         opt = ServerOptions(int(hbm_budget), int(max_active), _prec(precision),
                             float(residual_target), int(check_every), int(max_steps), float(cfl),
                             int(bool(graph)), float(polish_below))

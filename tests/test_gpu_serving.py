@@ -73,8 +73,9 @@ def test_admission_bounded_by_memory():
     _say("[gpu] serving under a memory budget")
     need = max(binding.required_bytes(r.nx, r.ny, r.p, binding.velocity_set(r.velset), 1.0,
                                       r.bc, r.wall_u) for r in REQS)
-    res, mom, st = _serve(REQS, [0.0] * len(REQS), precision="fp64", hbm_budget=2 * need + 1)
-    assert st["peak_active"] <= 2 and st["peak_bytes"] <= 2 * need + 1
+    budget = 2 * need + 1  # room for two of the largest request, never for all five
+    res, mom, st = _serve(REQS, [0.0] * len(REQS), precision="fp64", hbm_budget=budget)
+    assert st["peak_bytes"] <= budget and 2 <= st["peak_active"] < len(REQS)
     assert all(r["status"] == binding.REQ_CONVERGED for r in res)
     ref, mref, _ = _serve(REQS, [0.0] * len(REQS), precision="fp64")
     for a, b in zip(mom, mref):
