@@ -23,7 +23,7 @@ using namespace dgbgk;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kFusedLdsLimit = 64 * 1024;  // keeps >= 2 work-groups per CU
+constexpr size_t kFusedLdsLimit = 80 * 1024;  // keeps >= 2 work-groups per CU
 constexpr size_t kStreamLdsLimit = 160 * 1024;  // one persistent work-group per CU
 constexpr int kMaxQ = 4096;
 
@@ -186,10 +186,11 @@ void choose_tiling(dgbgk_solver *s) {
   const int NP = s->Np;
   const int G = kBlock / NP;
   int E = 1;
-  // for orders the persistent kernel serves, keep one velocity row per thread
-  const bool row_cap = s->p <= kStreamMaxP;
-  while (E * 2 <= G && (int64_t)E * 2 * s->Q * NP <= 4096 && E * 2 <= s->K &&
-         (!row_cap || (int64_t)E * 2 * s->Q <= kBlock))
+  // the persistent kernel takes one velocity row per thread
+  const bool row_cap = s->tiling_mode == 4 && s->p <= kStreamMaxP;
+  while (E * 2 <= G && (int64_t)E * 2 * s->Q * NP <= 8192 && E * 2 <= s->K &&
+         (!row_cap || (int64_t)E * 2 * s->Q <= kBlock) &&
+         stage_lds_bytes(s->p, E * 2, s->Q) <= kFusedLdsLimit)
     E *= 2;
   if (s->forced_E > 0) E = s->forced_E;
   size_t lds = stage_lds_bytes(s->p, E, s->Q);

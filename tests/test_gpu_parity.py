@@ -138,6 +138,7 @@ def test_persistent_and_per_block_kernels_identical(n, ny, p, m):
     a = binding.Solver.from_spec(spec)
     b = binding.Solver.from_spec(spec)
     a.set_tiling(4, 0)
+    b.set_block_elements(a.tiling()["elems_per_group"])  # the same blocks: same sums
     assert a.tiling()["persistent"] and b.tiling()["fused"] and not b.tiling()["persistent"]
     f = workloads.perturbed_state(5, a.w, a.K, a.Np, amp=0.05)
     assert np.array_equal(a.rhs(f), b.rhs(f))
