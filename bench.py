@@ -11,7 +11,9 @@ Prints one JSON line with the metric, a roofline object for the stage kernel
 (its average duration measured with HIP events on the stream it runs on), the
 CPU oracle timed on a bounded sample of the same workload, and the precision
 path (FP32 storage) measured on the same GPU: on this workload and on the
-precision workload (cavity 128x128 quads, p=4, NC 24x24, Kn=8) beside FP64.
+precision workload (cavity 128x128 quads, p=4, NC 24x24, Kn=8) beside FP64;
+batched and served mixes of problems; and the implicit (backward Euler,
+Newton-Krylov) steps beside explicit RK4.
 """
 import argparse
 import hashlib
@@ -223,6 +225,68 @@ def serving(n_requests, n_range=(16, 28)):
     return out
 
 
+def implicit_path(steps=2, mult=10.0, race_target=1e-6):
+    """Implicit backward-Euler steps (Newton with matrix-free GMRES, the
+    paper's time marching) on the benchmark cavity at 10 explicit step sizes,
+    against explicit RK4 covering the same simulated time; and a race to the
+    steady state (residual below race_target times its initial value) on a
+    small cavity (8x8 quads, p=2, NC 8x8, Kn=1): backward Euler at 5000
+    explicit step sizes against explicit RK4 at CFL 0.2."""
+    import torch
+
+    import workloads
+    from paper_2012_13487_amd import Solver
+
+    spec = workloads.CAVITY_64x64_P3_NC16
+    g = Solver.from_spec(spec)
+    g.init_equilibrium()
+    dt = g.stable_dt(spec.cfl)
+    g.implicit_step(1, mult * dt, "backward_euler")  # workspace allocation, warm-up
+    t0 = time.perf_counter()
+    rep = g.implicit_step(steps, mult * dt, "backward_euler")
+    imp_s = (time.perf_counter() - t0) / steps
+    g.synchronize()
+    t0 = time.perf_counter()
+    g.step(int(mult) * steps, dt)
+    g.synchronize()
+    exp_s = (time.perf_counter() - t0) / (int(mult) * steps)
+    out = {"workload": "cavity 64x64 p=3 NC16, backward Euler at dt = "
+                       f"{mult:g} x the explicit CFL-0.2 step, from rest",
+           "ms_per_step": imp_s * 1e3,
+           "newton_per_step": rep["newton_iterations"] / steps,
+           "krylov_per_step": rep["krylov_iterations"] / steps,
+           "rhs_evaluations_per_step": rep["rhs_evaluations"] / steps,
+           "simulated_time_per_s": mult * dt / imp_s,
+           "explicit_rk4_simulated_time_per_s": dt / exp_s}
+    out["implicit_over_explicit"] = out["simulated_time_per_s"] / out["explicit_rk4_simulated_time_per_s"]
+    del g
+
+    small = workloads.cavity(n=8, p=2, m=8, lid=0.1, kn=1.0)
+    race = {"workload": small.name, "target": f"residual < {race_target:g} x initial"}
+    g = Solver.from_spec(small)
+    g.init_equilibrium()
+    r0 = g.residual()
+    dts = g.stable_dt(small.cfl)
+    t0 = time.perf_counter()
+    n = 0
+    while g.residual() > race_target * r0 and n < 50:
+        g.implicit_step(1, 5000 * dts, "backward_euler", max_krylov=1000)
+        n += 1
+    race["backward_euler_s"] = time.perf_counter() - t0
+    race["backward_euler_steps"] = n
+    g.init_equilibrium()
+    t0 = time.perf_counter()
+    n = 0
+    while g.residual() > race_target * r0 and n < 400_000:
+        g.step(500, dts)
+        n += 500
+    race["explicit_rk4_s"] = time.perf_counter() - t0
+    race["explicit_rk4_steps"] = n
+    out["steady_state_race"] = race
+    torch.cuda.synchronize()
+    return out
+
+
 def _timed(fn):
     """Milliseconds of the device work `fn` enqueues on torch's current stream."""
     import torch
@@ -248,6 +312,7 @@ def main():
     ap.add_argument("--no-precision-path", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-implicit", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB (5 times), to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters of the stage kernel")
@@ -353,6 +418,8 @@ def main():
         out["batching"] = batching(10)
     if not args.no_serving:
         out["serving"] = serving(32)
+    if not args.no_implicit:
+        out["implicit"] = implicit_path()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_budget)
     print(json.dumps(out), flush=True)

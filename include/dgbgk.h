@@ -243,6 +243,61 @@ int dgbgk_set_block_elements(dgbgk_solver *s, int32_t elems_per_group);
  * solver's stream. */
 int dgbgk_autotune(dgbgk_solver *s, int32_t launches, double *best_us);
 
+/* ---- implicit time steps (the paper's time marching) ---------------------
+ *
+ * One step of a stiffly accurate singly diagonally implicit Runge-Kutta
+ * scheme, the family the paper integrates with (Sec. II.B, "Time marching"):
+ *   DGBGK_BACKWARD_EULER  1 stage, first order, L-stable;
+ *   DGBGK_SDIRK2          Alexander's 2-stage, second order, L-stable
+ *                         (gamma = 1 - 1/sqrt(2));
+ *   DGBGK_SDIRK4          5-stage, fourth order, L-stable, gamma = 1/4
+ *                         (Hairer and Wanner, Solving ODEs II, Sec. IV.6);
+ *                         the paper's fourth-order runs name four stages but
+ *                         give no coefficients, and no four-stage stiffly
+ *                         accurate scheme reaches fourth order.
+ * Stage i solves y_i = b_i + dt gamma L(y_i), b_i = f_n + dt sum_{j<i} a_ij L(y_j),
+ * by Newton's method with GMRES(m) on (I - dt gamma J) d = -F, the products
+ * J v taken matrix-free as (L(y + e v) - L(y)) / e with the same right-hand
+ * side kernels as the explicit path; f_{n+1} = y_s.  Vector reductions are
+ * deterministic, so a call is bitwise reproducible.  FP64 precision only
+ * (DGBGK_ENOTSUP otherwise).  The library allocates a device workspace of
+ * (m + stages + 6) state-sized vectors at the first call (kept until destroy,
+ * regrown if a later call needs more).  Norms are root-mean-square over all
+ * K Np Q values.  A stage's Newton iteration stops when its nonlinear residual
+ * |y - b - dt gamma L(y)| falls to newton_rtol times its value at the initial
+ * guess y = (previous stage value, f_n for the first stage), or to
+ * newton_atol; each GMRES solve stops at krylov_rtol times the Newton
+ * residual or a tenth of the Newton target, whichever is larger, after
+ * max_krylov iterations, or on breakdown.  The difference step is 1e-6
+ * (1 + |y|_2) for a unit vector.  opt may be NULL:
+ * max_newton 20, newton_rtol 1e-10, newton_atol 1e-14, restart 30,
+ * max_krylov 300, krylov_rtol 1e-6. */
+typedef enum { DGBGK_BACKWARD_EULER = 0, DGBGK_SDIRK2 = 1, DGBGK_SDIRK4 = 2 } dgbgk_implicit_scheme;
+
+typedef struct {
+  int32_t max_newton;   /* Newton iterations per stage (1..1000)          */
+  double newton_rtol;   /* >= 0                                           */
+  double newton_atol;   /* >= 0                                           */
+  int32_t restart;      /* GMRES restart length m (1..64)                 */
+  int32_t max_krylov;   /* GMRES iterations per Newton step (>= 1)        */
+  double krylov_rtol;   /* in (0, 1)                                      */
+} dgbgk_implicit_options;
+
+typedef struct {
+  int32_t newton_iterations;  /* summed over the stages                    */
+  int32_t krylov_iterations;  /* summed over the stages and Newton steps   */
+  int32_t rhs_evaluations;
+  double max_final_residual;  /* largest final stage residual (RMS)        */
+  int32_t converged;          /* every stage met the Newton tolerance      */
+} dgbgk_implicit_report;
+
+/* nsteps implicit steps of size dt (synchronises; report may be NULL).
+ * Returns DGBGK_ENONFINITE if a residual becomes non-finite; a stage that
+ * does not meet its tolerance within max_newton iterations still completes
+ * (report->converged = 0). */
+int dgbgk_implicit_step(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double dt,
+                        const dgbgk_implicit_options *opt, dgbgk_implicit_report *report);
+
 /* ---- batches: several problems advanced together ------------------------
  *
  * A batch advances n solvers (any mix of meshes, orders, velocity sets, Kn,

@@ -60,6 +60,23 @@ class ServerStats(C.Structure):
                 ("precision_switches", C.c_int64)]
 
 
+class ImplicitOptions(C.Structure):
+    """Mirror of dgbgk_implicit_options."""
+    _fields_ = [("max_newton", C.c_int32), ("newton_rtol", C.c_double),
+                ("newton_atol", C.c_double), ("restart", C.c_int32), ("max_krylov", C.c_int32),
+                ("krylov_rtol", C.c_double)]
+
+
+class ImplicitReport(C.Structure):
+    """Mirror of dgbgk_implicit_report."""
+    _fields_ = [("newton_iterations", C.c_int32), ("krylov_iterations", C.c_int32),
+                ("rhs_evaluations", C.c_int32), ("max_final_residual", C.c_double),
+                ("converged", C.c_int32)]
+
+
+BACKWARD_EULER, SDIRK2, SDIRK4 = 0, 1, 2
+SCHEMES = {"backward_euler": BACKWARD_EULER, "sdirk2": SDIRK2, "sdirk4": SDIRK4}
+
 REQ_WAITING, REQ_RUNNING, REQ_CONVERGED, REQ_STOPPED, REQ_FAILED = 0, 1, 2, 3, 4
 
 # name -> (restype, argtypes) for every function declared in include/dgbgk.h
@@ -85,6 +102,8 @@ SIGNATURES = {
     "dgbgk_state_device_ptr": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "dgbgk_step": (C.c_int, [C.c_void_p, C.c_int64, C.c_double]),
     "dgbgk_rhs": (C.c_int, [C.c_void_p, _dp, _dp, C.c_size_t]),
+    "dgbgk_implicit_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_double,
+                                      C.POINTER(ImplicitOptions), C.POINTER(ImplicitReport)]),
     "dgbgk_wall_density": (C.c_int, [C.c_void_p, _dp, _dp, C.c_size_t]),
     "dgbgk_residual": (C.c_int, [C.c_void_p, _dp]),
     "dgbgk_residual_async": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -341,6 +360,16 @@ class Solver:
 
     def step(self, nsteps, dt):
         self._call("dgbgk_step", int(nsteps), float(dt))
+
+    def implicit_step(self, nsteps, dt, scheme="backward_euler", max_newton=20, newton_rtol=1e-10,
+                      newton_atol=1e-14, restart=30, max_krylov=300, krylov_rtol=1e-6):
+        """nsteps SDIRK steps (Newton with matrix-free GMRES); returns the report as a dict."""
+        sc = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+        o = ImplicitOptions(int(max_newton), float(newton_rtol), float(newton_atol), int(restart),
+                            int(max_krylov), float(krylov_rtol))
+        r = ImplicitReport()
+        self._call("dgbgk_implicit_step", sc, int(nsteps), float(dt), C.byref(o), C.byref(r))
+        return {name: getattr(r, name) for name, _ in ImplicitReport._fields_}
 
     def rhs(self, f):
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)

@@ -17,6 +17,7 @@
 #include "host_math.hpp"
 #include "kernels.hpp"
 #include "kernels32.hpp"
+#include "linalg.hpp"
 
 using namespace dgbgk;
 
@@ -96,6 +97,9 @@ struct dgbgk_solver {
   size_t lds = 0;
   int tiling_mode = 0, tiling_qt = 0;
   int forced_E = 0;  // elements per work-group set by the caller or the autotuner (0: automatic)
+  // implicit-step workspace (allocated at the first implicit step)
+  double *imp_ws = nullptr;
+  size_t imp_bytes = 0;
   // state
   bool have_state = false;
   int64_t steps = 0;
@@ -632,6 +636,10 @@ void dgbgk_destroy(dgbgk_solver *s) {
     (void)hipStreamSynchronize(s->stream);
     (void)hipFree(s->base);
   }
+  if (s->imp_ws) {
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipFree(s->imp_ws);
+  }
   delete s;
 }
 
@@ -1060,6 +1068,370 @@ int dgbgk_autotune(dgbgk_solver *s, int32_t launches, double *best_us) {
   if (e != hipSuccess) return hip_fail(s, e, "autotune timing");
   if (best < 0.0) return fail(s, DGBGK_ENOTSUP, "no admissible configuration");
   if (best_us) *best_us = best;
+  return DGBGK_OK;
+}
+
+}  // extern "C"
+
+// ---- implicit SDIRK steps: Newton's method with matrix-free GMRES ---------
+
+namespace {
+
+// Stiffly accurate SDIRK tableaus (lower triangle of A, diagonal gamma);
+// f_{n+1} is the last stage value.
+struct Sdirk {
+  int stages = 0;
+  double gamma = 0.0;
+  double a[5][5] = {};
+};
+
+bool sdirk_tableau(int scheme, Sdirk &t) {
+  t = Sdirk{};
+  switch (scheme) {
+    case DGBGK_BACKWARD_EULER:
+      t.stages = 1;
+      t.gamma = 1.0;
+      break;
+    case DGBGK_SDIRK2: {  // Alexander (1977), two stages, L-stable
+      const double g = 1.0 - std::sqrt(0.5);
+      t.stages = 2;
+      t.gamma = g;
+      t.a[1][0] = 1.0 - g;
+      break;
+    }
+    case DGBGK_SDIRK4:  // Hairer-Wanner, five stages, order 4, L-stable
+      t.stages = 5;
+      t.gamma = 0.25;
+      t.a[1][0] = 0.5;
+      t.a[2][0] = 17.0 / 50.0;
+      t.a[2][1] = -1.0 / 25.0;
+      t.a[3][0] = 371.0 / 1360.0;
+      t.a[3][1] = -137.0 / 2720.0;
+      t.a[3][2] = 15.0 / 544.0;
+      t.a[4][0] = 25.0 / 24.0;
+      t.a[4][1] = -49.0 / 48.0;
+      t.a[4][2] = 125.0 / 16.0;
+      t.a[4][3] = -85.0 / 12.0;
+      break;
+    default:
+      return false;
+  }
+  for (int i = 0; i < t.stages; ++i) t.a[i][i] = t.gamma;
+  return true;
+}
+
+// Relative step of the forward differences J v ~ (L(y + e v) - L(y)) / e.
+// The rounding error of an evaluation of L is relative to its transport terms
+// (|D f|), which near uniform or steady states exceed |L| by orders of
+// magnitude, so the usual sqrt(machine epsilon) would leave that error
+// amplified by 1e8; 1e-6 balances it against the truncation error of the
+// quadratic equilibrium.
+constexpr double kFdStep = 1e-6;
+
+// Device workspace of one implicit step, in doubles: the stage rates, the
+// Newton vectors, the Krylov basis and the small reduction buffers.
+struct ImplicitWs {
+  size_t n = 0, stride = 0;
+  double *K = nullptr;  // stages x stride: L(y_i)
+  double *y = nullptr, *b = nullptr, *F = nullptr, *T = nullptr, *X = nullptr;
+  double *V = nullptr;  // (m + 1) x stride
+  double *dots = nullptr;   // multi-dot scratch
+  double *small = nullptr;  // h1[m+1], h2[m+1], |w|^2, spare
+  double *coef = nullptr;   // kMaxBasis coefficients uploaded from the host
+};
+
+size_t implicit_ws_bytes(size_t n, int stages, int m, size_t *stride) {
+  const size_t st = (n + 31) / 32 * 32;
+  if (stride) *stride = st;
+  const size_t vecs = (size_t)stages + 5 + (size_t)(m + 1);
+  const size_t small = multi_dot_scratch(n, m + 1) + 2 * (size_t)(m + 1) + 8 + kMaxBasis;
+  return (vecs * st + small) * sizeof(double);
+}
+
+struct Implicit {
+  dgbgk_solver *s;
+  ImplicitWs w;
+  int m;
+  double h = 0.0;         // dt gamma of the current stage
+  double eps = 0.0;       // finite-difference step for a unit vector
+  int rhs_evals = 0;
+  std::vector<double> host_small, host_coef;
+
+  double *Vk(int k) const { return w.V + (size_t)k * w.stride; }
+
+  int check(hipError_t e, const char *what) { return e == hipSuccess ? DGBGK_OK : hip_fail(s, e, what); }
+
+  // x . y, synchronised to the host.
+  int dot(const double *x, const double *y, double &out) {
+    int rc = check(launch_multi_dot(w.n, 1, x, w.stride, y, w.dots, w.small + 2 * (m + 1), s->stream),
+                   "dot kernel");
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(host_small.data(), w.small + 2 * (m + 1), sizeof(double),
+                                  hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "dot copy");
+    out = host_small[0];
+    return DGBGK_OK;
+  }
+
+  int rhs(const double *in, double *out) {
+    ++rhs_evals;
+    return run_stage(s, 0, in, out, 0.0);
+  }
+
+  // out = v - h (L(y + e v) - L(y)) / e with e = eps / vnorm: the product of
+  // (I - h J(y)) with v by a forward difference.  Ly = L(y); out != v.
+  int apply(const double *v, double vnorm, const double *Ly, double *out) {
+    const double e = eps / vnorm;
+    int rc = check(launch_lincomb(w.n, 1.0, w.y, e, v, 0.0, nullptr, w.T, s->stream), "lincomb");
+    if (!rc) rc = rhs(w.T, out);
+    if (!rc)
+      rc = check(launch_lincomb(w.n, -h / e, out, h / e, Ly, 1.0, v, out, s->stream), "lincomb");
+    return rc;
+  }
+
+  // GMRES(m) for (I - h J) X = -F from X = 0, Givens rotations on the host.
+  int gmres(const double *Ly, double fnorm2, double tol2, int max_it, int &iters) {
+    const size_t n = w.n;
+    std::vector<double> R((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), yv(m);
+    int rc = check(launch_lincomb(n, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, w.X, s->stream), "zero");
+    if (rc) return rc;
+    double beta = fnorm2;
+    rc = check(launch_lincomb(n, -1.0 / beta, w.F, 0.0, nullptr, 0.0, nullptr, Vk(0), s->stream),
+               "lincomb");
+    if (rc) return rc;
+    bool done = false;
+    while (!done) {
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int jn = 0;
+      for (int j = 0; j < m; ++j) {
+        double *v1 = Vk(j + 1);
+        if ((rc = apply(Vk(j), 1.0, Ly, v1))) return rc;
+        // Classical Gram-Schmidt, repeated only when the first pass cancels
+        // more than half of |w| (the "twice is enough" criterion).  V_0..V_j
+        // and w = V_{j+1} are consecutive, so one multi-dot over j + 2
+        // vectors gives the projections and |w|^2; without a second pass
+        // |w'|^2 = |w|^2 - |h|^2 and the normalisation joins the update.
+        double *h1 = w.small, *h2 = w.small + (m + 1);
+        hipError_t e = launch_multi_dot(n, j + 2, w.V, w.stride, v1, w.dots, h1, s->stream);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(host_small.data(), h1, (size_t)(j + 2) * sizeof(double),
+                             hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return hip_fail(s, e, "Arnoldi projections");
+        double *col = &R[(size_t)j * (m + 1)];
+        double hh = 0.0;
+        for (int i = 0; i <= j; ++i) {
+          col[i] = host_small[i];
+          hh += col[i] * col[i];
+        }
+        const double ww = host_small[j + 1];
+        if (!std::isfinite(ww) || !std::isfinite(hh))
+          return fail(s, DGBGK_ENONFINITE, "Krylov vector is not finite");
+        double hn;
+        if (ww - hh > 0.5 * ww) {
+          hn = std::sqrt(ww - hh);
+          e = launch_multi_axpy(n, j + 1, w.V, w.stride, h1, -1.0, v1, 1.0 / hn, v1, s->stream);
+        } else {
+          e = launch_multi_axpy(n, j + 1, w.V, w.stride, h1, -1.0, v1, 1.0, v1, s->stream);
+          if (e == hipSuccess) e = launch_multi_dot(n, j + 2, w.V, w.stride, v1, w.dots, h2, s->stream);
+          if (e == hipSuccess)
+            e = hipMemcpyAsync(host_small.data(), h2, (size_t)(j + 2) * sizeof(double),
+                               hipMemcpyDeviceToHost, s->stream);
+          if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+          if (e != hipSuccess) return hip_fail(s, e, "Arnoldi reorthogonalisation");
+          double hh2 = 0.0;
+          for (int i = 0; i <= j; ++i) {
+            col[i] += host_small[i];
+            hh2 += host_small[i] * host_small[i];
+          }
+          hn = std::sqrt(std::max(host_small[j + 1] - hh2, 0.0));
+          e = launch_multi_axpy(n, j + 1, w.V, w.stride, h2, -1.0, v1, hn > 0.0 ? 1.0 / hn : 1.0, v1,
+                                s->stream);
+        }
+        if (e != hipSuccess) return hip_fail(s, e, "Arnoldi update");
+        for (int i = 0; i < j; ++i) {
+          const double a = col[i], b = col[i + 1];
+          col[i] = cs[i] * a + sn[i] * b;
+          col[i + 1] = -sn[i] * a + cs[i] * b;
+        }
+        const double den = std::hypot(col[j], hn);
+        cs[j] = den > 0 ? col[j] / den : 1.0;
+        sn[j] = den > 0 ? hn / den : 0.0;
+        col[j] = den;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++iters;
+        jn = j + 1;
+        const bool breakdown = !(hn > 0.0);
+        if (std::fabs(g[j + 1]) <= tol2 || breakdown || iters >= max_it) {
+          done = true;
+          break;
+        }
+      }
+      // X += V y with R y = g (upper triangular, jn columns)
+      for (int i = jn - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int k = i + 1; k < jn; ++k) t -= R[(size_t)k * (m + 1) + i] * yv[k];
+        const double d = R[(size_t)i * (m + 1) + i];
+        yv[i] = d != 0.0 ? t / d : 0.0;
+      }
+      for (int i = 0; i < jn; ++i) host_coef[i] = yv[i];
+      hipError_t e = hipMemcpyAsync(w.coef, host_coef.data(), jn * sizeof(double),
+                                    hipMemcpyHostToDevice, s->stream);
+      if (e == hipSuccess)
+        e = launch_multi_axpy(n, jn, w.V, w.stride, w.coef, 1.0, w.X, 1.0, w.X, s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // host_coef is reused
+      if (e != hipSuccess) return hip_fail(s, e, "GMRES update");
+      if (done) break;
+      // restart from the true residual -F - (I - h J) X
+      double xn2 = 0.0;
+      if ((rc = dot(w.X, w.X, xn2))) return rc;
+      const double xn = std::sqrt(xn2);
+      if (!(xn > 0.0)) break;
+      if ((rc = apply(w.X, xn, Ly, Vk(0)))) return rc;
+      if ((rc = check(launch_lincomb(n, -1.0, Vk(0), -1.0, w.F, 0.0, nullptr, Vk(0), s->stream),
+                      "lincomb")))
+        return rc;
+      double r2 = 0.0;
+      if ((rc = dot(Vk(0), Vk(0), r2))) return rc;
+      beta = std::sqrt(r2);
+      if (!std::isfinite(beta)) return fail(s, DGBGK_ENONFINITE, "GMRES residual is not finite");
+      if (beta <= tol2) break;
+      if ((rc = check(launch_lincomb(n, 1.0 / beta, Vk(0), 0.0, nullptr, 0.0, nullptr, Vk(0), s->stream),
+                      "lincomb")))
+        return rc;
+    }
+    return DGBGK_OK;
+  }
+
+  // F = y - b - h Ly and its 2-norm.
+  int newton_residual(const double *Ly, double &fn2) {
+    int rc = check(launch_lincomb(w.n, 1.0, w.y, -1.0, w.b, -h, Ly, w.F, s->stream), "lincomb");
+    double ff = 0.0;
+    if (!rc) rc = dot(w.F, w.F, ff);
+    if (rc) return rc;
+    fn2 = std::sqrt(ff);
+    if (!std::isfinite(fn2)) return fail(s, DGBGK_ENONFINITE, "Newton residual is not finite");
+    return DGBGK_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int dgbgk_implicit_step(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double dt,
+                        const dgbgk_implicit_options *opt, dgbgk_implicit_report *report) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  Sdirk tab;
+  if (!sdirk_tableau(scheme, tab)) return fail(s, DGBGK_EINVAL, "unknown implicit scheme %d", scheme);
+  if (nsteps < 0 || !(dt > 0) || !is_finite_d(dt)) return fail(s, DGBGK_EINVAL, "need nsteps >= 0, dt > 0");
+  dgbgk_implicit_options o{20, 1e-10, 1e-14, 30, 300, 1e-6};
+  if (opt) o = *opt;
+  if (o.max_newton < 1 || o.max_newton > 1000 || o.restart < 1 || o.restart > 64 || o.max_krylov < 1 ||
+      !(o.newton_rtol >= 0) || !(o.newton_atol >= 0) || !is_finite_d(o.newton_rtol) ||
+      !is_finite_d(o.newton_atol) || !(o.krylov_rtol > 0 && o.krylov_rtol < 1))
+    return fail(s, DGBGK_EINVAL, "implicit options out of range");
+  if (s->prec != DGBGK_FP64) return fail(s, DGBGK_ENOTSUP, "implicit steps need FP64 precision");
+  if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  if (report) *report = dgbgk_implicit_report{0, 0, 0, 0.0, 1};
+
+  Implicit im{s, ImplicitWs{}, o.restart};
+  const size_t n = (size_t)s->K * s->Np * s->Q;
+  size_t stride = 0;
+  const size_t bytes = implicit_ws_bytes(n, tab.stages, im.m, &stride);
+  if (bytes > s->imp_bytes) {
+    if (s->imp_ws) {
+      (void)hipStreamSynchronize(s->stream);
+      (void)hipFree(s->imp_ws);
+      s->imp_ws = nullptr;
+      s->imp_bytes = 0;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return fail(s, DGBGK_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    s->imp_ws = (double *)p;
+    s->imp_bytes = bytes;
+  }
+  ImplicitWs &w = im.w;
+  w.n = n;
+  w.stride = stride;
+  double *q = s->imp_ws;
+  w.K = q;  q += (size_t)tab.stages * stride;
+  w.y = q;  q += stride;
+  w.b = q;  q += stride;
+  w.F = q;  q += stride;
+  w.T = q;  q += stride;
+  w.X = q;  q += stride;
+  w.V = q;  q += (size_t)(im.m + 1) * stride;
+  w.dots = q;  q += multi_dot_scratch(n, im.m + 1);
+  w.small = q;  q += 2 * (size_t)(im.m + 1) + 8;
+  w.coef = q;
+  im.host_small.assign(2 * (size_t)(im.m + 1) + 8, 0.0);
+  im.host_coef.assign(kMaxBasis, 0.0);
+
+  const double rms = std::sqrt((double)n);  // 2-norm -> RMS
+  int newton_total = 0, krylov_total = 0;
+  double worst = 0.0;
+  bool all_conv = true;
+  for (int64_t step = 0; step < nsteps; ++step) {
+    for (int i = 0; i < tab.stages; ++i) {
+      // b_i = f_n + dt sum_{j<i} a_ij k_j
+      for (int j = 0; j < i; ++j) im.host_coef[j] = dt * tab.a[i][j];
+      hipError_t e = hipSuccess;
+      if (i > 0)
+        e = hipMemcpyAsync(w.coef, im.host_coef.data(), i * sizeof(double), hipMemcpyHostToDevice,
+                           s->stream);
+      if (e == hipSuccess)
+        e = launch_multi_axpy(n, i, w.K, stride, w.coef, 1.0, s->d_fn, 1.0, w.b, s->stream);
+      if (e == hipSuccess && i == 0)
+        e = launch_lincomb(n, 1.0, s->d_fn, 0.0, nullptr, 0.0, nullptr, w.y, s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // host_coef is reused
+      if (e != hipSuccess) return hip_fail(s, e, "stage set-up");
+      im.h = dt * tab.gamma;
+      double *Ly = w.K + (size_t)i * stride;
+      if ((rc = im.rhs(w.y, Ly))) return rc;
+      double fn2 = 0.0;
+      if ((rc = im.newton_residual(Ly, fn2))) return rc;
+      const double target = std::max(o.newton_rtol * fn2, o.newton_atol * rms);
+      bool conv = fn2 <= target;
+      for (int it = 0; it < o.max_newton && !conv; ++it) {
+        double yy = 0.0;
+        if ((rc = im.dot(w.y, w.y, yy))) return rc;
+        im.eps = kFdStep * (1.0 + std::sqrt(yy));
+        int kit = 0;
+        // inexact Newton: no linear solve tighter than the Newton target needs
+        const double ktol = std::max(o.krylov_rtol * fn2, 0.1 * target);
+        if ((rc = im.gmres(Ly, fn2, ktol, o.max_krylov, kit))) return rc;
+        krylov_total += kit;
+        ++newton_total;
+        if ((rc = im.check(launch_lincomb(n, 1.0, w.y, 1.0, w.X, 0.0, nullptr, w.y, s->stream), "lincomb")))
+          return rc;
+        if ((rc = im.rhs(w.y, Ly))) return rc;
+        if ((rc = im.newton_residual(Ly, fn2))) return rc;
+        conv = fn2 <= target;
+      }
+      all_conv = all_conv && conv;
+      worst = std::max(worst, fn2 / rms);
+    }
+    // stiffly accurate: f_{n+1} is the last stage value
+    hipError_t e = launch_lincomb(n, 1.0, w.y, 0.0, nullptr, 0.0, nullptr, s->d_fn, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "lincomb");
+    ++s->steps;
+  }
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "implicit step");
+  if (report) {
+    report->newton_iterations = newton_total;
+    report->krylov_iterations = krylov_total;
+    report->rhs_evaluations = im.rhs_evals;
+    report->max_final_residual = worst;
+    report->converged = all_conv ? 1 : 0;
+  }
   return DGBGK_OK;
 }
 

@@ -1,0 +1,144 @@
+// FP64 vector kernels of the implicit time step: a fused linear combination,
+// a deterministic multi-vector dot product (Gram-Schmidt projections of the
+// Krylov basis) and the matching multi-vector update with scaling.  All are HBM-bound
+// streams; the dot kernel reads w once per four basis vectors.
+#include "linalg.hpp"
+
+namespace dgbgk {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 8;     // elements per thread per pass of the dot kernel
+constexpr int kVecs = 4;      // basis vectors per dot work-group
+constexpr int kMaxGroups = 1024;
+
+__global__ __launch_bounds__(kBlock) void lincomb_kernel(size_t n, double a, const double *x, double b,
+                                                         const double *y, double c, const double *z,
+                                                         double *out) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double v = x ? a * x[i] : 0.0;
+    if (y) v += b * y[i];
+    if (z) v += c * z[i];
+    out[i] = v;
+  }
+}
+
+// Sum of v over the work-group, valid in thread 0; red is reusable on return.
+__device__ inline double block_sum(double v, double *red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// Work-group (g, j) sums V_k . w for k = kVecs j ... kVecs j + kVecs - 1 over
+// the chunks g, g + G, g + 2G, ... of kBlock * kItems elements.
+__global__ __launch_bounds__(kBlock) void multi_dot_partial_kernel(size_t n, int nv, const double *V,
+                                                                   size_t vstride, const double *w,
+                                                                   double *partial) {
+  __shared__ double red[kBlock / 64];
+  const int k0 = blockIdx.y * kVecs;
+  const int G = gridDim.x;
+  double acc[kVecs];
+#pragma unroll
+  for (int t = 0; t < kVecs; ++t) acc[t] = 0.0;
+  const size_t chunk = (size_t)kBlock * kItems;
+  for (size_t base = (size_t)blockIdx.x * chunk; base < n; base += (size_t)G * chunk) {
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const size_t i = base + (size_t)it * kBlock + threadIdx.x;
+      if (i < n) {
+        const double wi = w[i];
+#pragma unroll
+        for (int t = 0; t < kVecs; ++t)
+          if (k0 + t < nv) acc[t] += V[(size_t)(k0 + t) * vstride + i] * wi;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kVecs; ++t) {
+    const double s = block_sum(acc[t], red);
+    if (threadIdx.x == 0 && k0 + t < nv) partial[(size_t)(k0 + t) * G + blockIdx.x] = s;
+  }
+}
+
+// Work-group k sums the G partials of vector k in a fixed order.
+__global__ __launch_bounds__(kBlock) void multi_dot_final_kernel(int G, const double *partial,
+                                                                 double *result) {
+  __shared__ double red[kBlock / 64];
+  const double *p = partial + (size_t)blockIdx.x * G;
+  double acc = 0.0;
+  for (int g = threadIdx.x; g < G; g += kBlock) acc += p[g];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) result[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void multi_axpy_kernel(size_t n, int nv, const double *V,
+                                                            size_t vstride, const double *coef,
+                                                            double alpha, const double *w,
+                                                            double scale, double *out) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double s = 0.0;
+    for (int k = 0; k < nv; ++k) s += coef[k] * V[(size_t)k * vstride + i];
+    out[i] = scale * (w[i] + alpha * s);
+  }
+}
+
+int dot_groups(size_t n) {
+  const size_t chunk = (size_t)kBlock * kItems;
+  size_t g = (n + chunk - 1) / chunk;
+  if (g < 1) g = 1;
+  return (int)(g > (size_t)kMaxGroups ? kMaxGroups : g);
+}
+
+unsigned stream_blocks(size_t n) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  return (unsigned)(b > 8192 ? 8192 : b);
+}
+
+}  // namespace
+
+hipError_t launch_lincomb(size_t n, double a, const double *x, double b, const double *y, double c,
+                          const double *z, double *out, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(lincomb_kernel, dim3(stream_blocks(n)), dim3(kBlock), 0, st, n, a, x, b, y, c,
+                     z, out);
+  return hipGetLastError();
+}
+
+size_t multi_dot_scratch(size_t n, int nv) { return (size_t)dot_groups(n) * (size_t)nv; }
+
+hipError_t launch_multi_dot(size_t n, int nv, const double *V, size_t vstride, const double *w,
+                            double *scratch, double *result, hipStream_t st) {
+  if (nv < 1 || nv > kMaxBasis) return hipErrorInvalidValue;
+  const int G = dot_groups(n);
+  const unsigned gy = (unsigned)((nv + kVecs - 1) / kVecs);
+  hipLaunchKernelGGL(multi_dot_partial_kernel, dim3((unsigned)G, gy), dim3(kBlock), 0, st, n, nv, V,
+                     vstride, w, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(multi_dot_final_kernel, dim3((unsigned)nv), dim3(kBlock), 0, st, G, scratch,
+                     result);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy(size_t n, int nv, const double *V, size_t vstride, const double *coef,
+                             double alpha, const double *w, double scale, double *out,
+                             hipStream_t st) {
+  if (nv < 0 || nv > kMaxBasis) return hipErrorInvalidValue;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(multi_axpy_kernel, dim3(stream_blocks(n)), dim3(kBlock), 0, st, n, nv, V,
+                     vstride, coef, alpha, w, scale, out);
+  return hipGetLastError();
+}
+
+}  // namespace dgbgk

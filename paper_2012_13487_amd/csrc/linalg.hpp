@@ -1,0 +1,34 @@
+// FP64 vector kernels of the implicit (Newton-Krylov) time step.  Every
+// reduction has a fixed assignment of elements to work-groups and a fixed
+// summation order for a given length, so results are bitwise reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace dgbgk {
+
+// Most vectors one multi-dot or multi-axpy call takes.
+constexpr int kMaxBasis = 72;
+
+// out = a x + b y + c z; a term is skipped when its pointer is null.  out may
+// alias any input (element-wise update).
+hipError_t launch_lincomb(size_t n, double a, const double *x, double b, const double *y, double c,
+                          const double *z, double *out, hipStream_t stream);
+
+// Doubles of scratch that launch_multi_dot needs for length n and nv vectors.
+size_t multi_dot_scratch(size_t n, int nv);
+
+// result[k] = V_k . w for k < nv, V_k = V + k * stride (nv <= kMaxBasis).
+// scratch holds multi_dot_scratch(n, nv) doubles; result is device memory.
+hipError_t launch_multi_dot(size_t n, int nv, const double *V, size_t stride, const double *w,
+                            double *scratch, double *result, hipStream_t stream);
+
+// out = scale (w + alpha sum_{k < nv} coef[k] V_k), coef in device memory
+// (nv <= kMaxBasis); out may alias w.
+hipError_t launch_multi_axpy(size_t n, int nv, const double *V, size_t stride, const double *coef,
+                             double alpha, const double *w, double scale, double *out,
+                             hipStream_t stream);
+
+}  // namespace dgbgk

@@ -172,6 +172,12 @@ def test_device_calls_fail_loudly_without_gpu():
     with pytest.raises(binding.DgbgkError) as ei:
         s.step(1, 1e-3)
     assert ei.value.code == binding.ESTATE
+    with pytest.raises(binding.DgbgkError) as ei:
+        s.implicit_step(1, 1e-3, "sdirk4")
+    assert ei.value.code == binding.ESTATE
+    with pytest.raises(binding.DgbgkError) as ei:
+        s.implicit_step(1, 1e-3, scheme=9)
+    assert ei.value.code == binding.EINVAL
 
 
 def test_server_validation_and_cpu_failure_path():

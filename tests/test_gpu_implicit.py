@@ -1,0 +1,175 @@
+"""GPU parity of the implicit SDIRK steps (Sec. II.B, "Time marching"): the
+library's Newton / matrix-free GMRES steps through the C ABI against the
+oracle's Newton steps with a dense Jacobian, on the same seeded states.
+
+Both sides solve the same stage equations to a tolerance, not by the same
+arithmetic, so the bar is set by the solver tolerances rather than by
+rounding: with newton_rtol = 1e-13 the stage residual is below 1e-13 of its
+initial value, and the state error is of the same relative size (the stage
+operators I - dt gamma J are well conditioned at these step sizes), far
+inside the 1e-10 relative max-norm asserted here.  At the full cavity size,
+where the oracle cannot form a dense Jacobian, the GPU result is checked
+against the backward-Euler equation itself, evaluated with the oracle's
+right-hand side."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import implicit
+from paper_2012_13487_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+TIGHT = dict(newton_rtol=1e-13, newton_atol=1e-17, krylov_rtol=1e-8, max_krylov=400)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+CASES = [
+    ("cavity_3x2_p2_nc4", workloads.cavity(n=3, ny=2, p=2, m=4, lid=0.2, kn=0.5), None),
+    ("couette_2x3_p1_gh4", workloads.couette(nx=2, ny=3, p=1, kn=2.0), None),
+    ("cavity_2x2_p3_nc5_tiled", workloads.cavity(n=2, p=3, m=5, lid=0.1), (2, 10)),
+    ("periodic_3x2_p2_gh3_persistent",
+     workloads.periodic_box(nx=3, ny=2, p=2, velset=("gh", 3), kn=0.3), (4, 0)),
+]
+
+
+@pytest.mark.parametrize("scheme,nsteps,cfl_mult", [("backward_euler", 2, 10.0), ("sdirk2", 1, 10.0),
+                                                    ("sdirk4", 1, 5.0)])
+@pytest.mark.parametrize("name,spec,tiling", CASES, ids=[c[0] for c in CASES])
+def test_implicit_step_parity(oracle_mod, name, spec, tiling, scheme, nsteps, cfl_mult):
+    _say(f"[gpu] implicit parity {name} {scheme} x{nsteps}")
+    g = binding.Solver.from_spec(spec)
+    if tiling is not None:
+        g.set_tiling(*tiling)
+    o = oracle_mod.Oracle.from_spec(spec)
+    f0 = workloads.perturbed_state(21, o.w, o.K, o.Np, amp=0.15)
+    dt = cfl_mult * o.stable_dt(0.2)
+    g.set_state(f0)
+    rep = g.implicit_step(nsteps, dt, scheme, **TIGHT)
+    assert rep["converged"] == 1, rep
+    fo = implicit.implicit_step(o, scheme, nsteps, dt, f0)
+    fg = g.get_state()
+    assert _rel(fg, fo) < TOL, (name, scheme, _rel(fg, fo), rep)
+    rg, uxg, uyg = g.moments()
+    ro, uxo, uyo = o.moments()
+    assert _rel(rg, ro) < TOL
+    u_o = np.stack([uxo, uyo])
+    assert np.max(np.abs(np.stack([uxg, uyg]) - u_o)) < TOL * max(np.max(np.abs(u_o)), 1e-3)
+    assert g.steps_taken() == nsteps
+
+
+def test_uniform_relaxation_closed_form(oracle_mod):
+    """Uniform state on a periodic box: backward Euler gives
+    f^eq + (f0 - f^eq) / (1 + dt / tau) exactly."""
+    _say("[gpu] implicit uniform relaxation")
+    spec = workloads.periodic_box(nx=8, ny=8, p=3, velset=("gh", 4), kn=0.5)
+    g = binding.Solver.from_spec(spec)
+    o = oracle_mod.Oracle.from_spec(spec)
+    rng = np.random.default_rng(31)
+    fq = o.w * (1.0 + 0.2 * rng.uniform(-1, 1, size=o.Q))
+    f0 = np.broadcast_to(fq[:, None, None], o.shape).copy()
+    rho = fq.sum()
+    feq = o.equilibrium(rho, (fq * o.ex).sum() / rho, (fq * o.ey).sum() / rho)[:, None, None]
+    for ratio in (0.5, 40.0):
+        g.set_state(f0)
+        g.implicit_step(1, ratio * o.tau, "backward_euler", **TIGHT)
+        want = feq + (f0 - feq) / (1.0 + ratio)
+        err = np.max(np.abs(g.get_state() - want))
+        assert err < 1e-12 * np.max(np.abs(f0 - feq)) * (1.0 + ratio), (ratio, err)
+
+
+def test_implicit_step_is_deterministic():
+    _say("[gpu] implicit determinism")
+    spec = workloads.cavity(n=12, p=3, m=8, lid=0.1)
+    out = []
+    for _ in range(2):
+        g = binding.Solver.from_spec(spec)
+        f0 = workloads.perturbed_state(4, g.w, g.K, g.Np, amp=0.1)
+        g.set_state(f0)
+        rep = g.implicit_step(2, 8 * g.stable_dt(0.2), "sdirk2")
+        out.append((g.get_state(), rep))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+
+
+def test_large_backward_euler_steps_reach_steady_state():
+    """With dt = 5000 explicit step sizes, backward Euler converges to the
+    steady state L(f) = 0 in a few steps (the paper's cavity runs march with
+    backward Euler): the residual falls monotonically by six orders of
+    magnitude in six steps."""
+    _say("[gpu] implicit steady state")
+    spec = workloads.cavity(n=8, p=2, m=8, lid=0.1, kn=1.0)
+    g = binding.Solver.from_spec(spec)
+    g.init_equilibrium()
+    r0 = g.residual()
+    dt = 5000 * g.stable_dt(0.2)
+    res = []
+    for _ in range(6):
+        rep = g.implicit_step(1, dt, "backward_euler", max_krylov=1000)
+        assert rep["converged"] == 1, rep
+        res.append(g.residual())
+    _say(f"  residuals {r0:.3e} -> {[f'{r:.2e}' for r in res]}")
+    assert res[-1] < 1e-6 * r0
+    assert all(res[i + 1] < res[i] for i in range(len(res) - 1))
+
+
+def test_full_size_backward_euler_satisfies_its_equation(oracle_mod):
+    """Lid-driven cavity 64 x 64, p = 3, NC 16 x 16: one backward-Euler step
+    of 10 explicit step sizes; the result y must satisfy
+    y - f0 - dt L(y) = 0 with L the oracle's right-hand side, and conserve
+    mass."""
+    spec = workloads.CAVITY_64x64_P3_NC16
+    _say(f"[gpu] implicit full size {spec.name}")
+    g = binding.Solver.from_spec(spec)
+    f0 = workloads.perturbed_state(6, g.w, g.K, g.Np, amp=0.05)
+    g.set_state(f0)
+    dt = 10 * g.stable_dt(0.2)
+    rep = g.implicit_step(1, dt, "backward_euler", newton_rtol=1e-12)
+    _say(f"  report {rep}")
+    assert rep["converged"] == 1, rep
+    y = g.get_state()
+    o = oracle_mod.Oracle.from_spec(spec)
+    resid = y - f0 - dt * o.rhs(y)
+    assert np.max(np.abs(resid)) < 1e-9 * np.max(np.abs(y - f0)), np.max(np.abs(resid))
+    o.set_state(f0)
+    m0 = o.total_mass()
+    o.set_state(y)
+    assert abs(o.total_mass() - m0) < 1e-12 * m0
+
+
+def test_implicit_step_errors():
+    _say("[gpu] implicit errors")
+    spec = workloads.cavity(n=4, p=2, m=4)
+    g = binding.Solver.from_spec(spec)
+    with pytest.raises(binding.DgbgkError) as ei:
+        g.implicit_step(1, 1e-3)
+    assert ei.value.code == binding.ESTATE
+    g.init_equilibrium()
+    with pytest.raises(binding.DgbgkError) as ei:
+        g.implicit_step(1, 1e-3, scheme=7)
+    assert ei.value.code == binding.EINVAL
+    with pytest.raises(binding.DgbgkError) as ei:
+        g.implicit_step(1, 1e-3, restart=0)
+    assert ei.value.code == binding.EINVAL
+    with pytest.raises(binding.DgbgkError) as ei:
+        g.implicit_step(1, -1.0)
+    assert ei.value.code == binding.EINVAL
+    g32 = binding.Solver.from_spec(spec, precision="fp32")
+    g32.init_equilibrium()
+    with pytest.raises(binding.DgbgkError) as ei:
+        g32.implicit_step(1, 1e-3)
+    assert ei.value.code == binding.ENOTSUP
+    # zero steps is a no-op
+    g.implicit_step(0, 1e-3)
+    assert g.steps_taken() == 0
