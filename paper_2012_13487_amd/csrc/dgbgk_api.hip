@@ -30,6 +30,13 @@ constexpr int kMaxQ = 4096;
 
 size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// MI355X last-level cache (Infinity Cache).  A stage touches four state
+// arrays; when they fit, the streams read once per stage are left cached
+// (the next stages find them there); above it they move with non-temporal
+// hints so that the neighbour tiles stay in L2 (measured both ways).
+constexpr size_t kLastLevelCacheBytes = (size_t)256 << 20;
+int stream_nt_for(size_t state_bytes) { return 4 * state_bytes > kLastLevelCacheBytes ? 1 : 0; }
+
 struct Layout {
   size_t fn, acc, a, b, xfer, vel, feqb, wmom, dmat, mom, rhow, u64, total;
 };
@@ -359,6 +366,7 @@ StageArgs base_args(const dgbgk_solver *s) {
   a.periodic_x = s->pb.bc[1] == DGBGK_BC_PERIODIC;
   a.periodic_y = s->pb.bc[0] == DGBGK_BC_PERIODIC;
   a.fused = s->fused;
+  a.stream_nt = stream_nt_for((size_t)s->K * s->Np * s->Q * sizeof(double));
   return a;
 }
 
@@ -395,6 +403,7 @@ Stage32Args base_args32(const dgbgk_solver *s) {
   a.wall_mask = s->wall_mask;
   a.periodic_x = s->pb.bc[1] == DGBGK_BC_PERIODIC;
   a.periodic_y = s->pb.bc[0] == DGBGK_BC_PERIODIC;
+  a.stream_nt = stream_nt_for((size_t)s->K * s->Np * s->Q * sizeof(float));
   return a;
 }
 
@@ -1490,6 +1499,10 @@ void stage_buffers(dgbgk_solver *s, int stage, void *&fs, void *&out) {
 
 // Fills the host copy of the descriptors of every class, stage and member.
 void fill_descriptors(dgbgk_batch *b, const double *dt) {
+  // the cache policy follows the whole batch's state, which a step sweeps
+  size_t total = 0;
+  for (dgbgk_solver *s : b->s) total += (size_t)s->K * s->Np * s->Q * (is_fp32(s->prec) ? 4 : 8);
+  const int nt = stream_nt_for(total);
   for (auto &c : b->cls) {
     const size_t nm = c.members.size();
     for (int stage = 0; stage <= 4; ++stage)
@@ -1510,6 +1523,7 @@ void fill_descriptors(dgbgk_batch *b, const double *dt) {
           a.stage = stage;
           a.c_acc = (float)ca;
           a.c_out = (float)co;
+          a.stream_nt = nt;
           std::memcpy(dst, &a, sizeof a);
         } else {
           StageArgs a = base_args(s);
@@ -1520,6 +1534,7 @@ void fill_descriptors(dgbgk_batch *b, const double *dt) {
           a.stage = stage;
           a.c_acc = ca;
           a.c_out = co;
+          a.stream_nt = nt;
           std::memcpy(dst, &a, sizeof a);
         }
       }

@@ -95,6 +95,33 @@ __device__ inline int xcd_block(int b, int nblk) {
   return x * per + (x < rem ? x : rem) + (b >> 3);
 }
 
+// Elements per strip of the strip order below (measured best on the
+// 64 x 64 p = 3 cavity in FP64 and FP32 and on the 128 x 128 p = 4 cavity).
+constexpr int kStripElems = 16;
+
+// The t-th element block in strip order: the block grid (rows of bpr blocks)
+// is cut into strips of kStripElems elements, each swept row by row, so that the
+// work-groups resident on one XCD at a time cover a compact patch and find
+// the faces of their neighbours above and below in L2.  Applies when the
+// blocks tile whole mesh rows (E divides nx); otherwise the identity.
+__device__ inline int strip_block(int t, int nx, int log2E, int nblk) {
+  if (nx & ((1 << log2E) - 1)) return t;
+  const int W = kStripElems >> log2E > 0 ? kStripElems >> log2E : 1;  // blocks per strip
+  const int bpr = nx >> log2E, rows = nblk / bpr;
+  const int full = bpr - bpr % W;  // columns in full-width strips
+  int row, col;
+  if (t < full * rows) {
+    const int per = W * rows, s = t / per, in = t - s * per;
+    row = in / W;
+    col = s * W + in % W;
+  } else {
+    const int wr = bpr - full, t2 = t - full * rows;
+    row = t2 / wr;
+    col = full + t2 % wr;
+  }
+  return row * bpr + col;
+}
+
 // LDS rows have an odd stride, so 16-byte values move as two 8-byte halves.
 __device__ __forceinline__ void lds_put(double *p, double v) { *p = v; }
 __device__ __forceinline__ void lds_put(double *p, const double2v &v) { *reinterpret_cast<double2v *>(p) = v; }
@@ -445,6 +472,76 @@ __device__ __forceinline__ void row_rhs(const StageArgs &a, double *row, const d
   }
 }
 
+// Loads and stores of the streams that are touched once per stage, with or
+// without non-temporal hints.
+template <bool NT, typename V>
+__device__ __forceinline__ V ld_once(const double *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+  return *reinterpret_cast<const V *>(p);
+}
+template <bool NT, typename V>
+__device__ __forceinline__ void st_once(double *p, const V &v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+  else *reinterpret_cast<V *>(p) = v;
+}
+
+// Phase 4 of a stage: the RK4 register update of the block, coalesced over
+// each velocity row; L(f) of the block is in the LDS tile.  With NT, x and
+// the accumulator, read once per stage and not again before the next
+// launch, move with non-temporal hints so that they do not evict the tiles
+// neighbours still gather from (used when the state arrays exceed the
+// last-level cache); the stage output, the next stage's input, is always
+// stored normally.
+template <int P, int MODE, bool NT>
+__device__ __forceinline__ void update_rows(const StageArgs &a, const double *tile, size_t boff, int Qb,
+                                            int E, int Eb, int nch, bool full, int tid, int nthr) {
+  using Sh = Shape<P>;
+  constexpr int NP = Sh::NP, S = Sh::S;
+  constexpr int CW = Sh::VEC ? 2 : 1;
+  constexpr int CPE = NP / CW;
+  constexpr int U = 8;
+  using V = typename std::conditional<Sh::VEC, double2v, double>::type;
+  const size_t QNP = (size_t)a.Q * NP;
+  const double cacc = a.c_acc, cout = a.c_out;
+  // x: f_s (stage 1), f_n (stages 2, 3), acc (stage 4); y: acc (stages 2, 3)
+  const double *xr = (MODE == 1 ? a.fs : MODE == 2 ? a.fn : a.acc) + boff;
+  double *accr = a.acc + boff;
+  double *outr = a.out + boff;
+  for (int c0 = tid; c0 < nch; c0 += nthr * U) {
+    V kv[U], x[U], y[U];
+    size_t go[U];
+    bool ok[U];
+    const bool all = full && c0 - tid + U * nthr <= nch;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * nthr;
+      int q, e, w;
+      split_access<CPE>(c, Qb, E, q, e, w);
+      ok[u] = all || (c < nch && e < Eb);
+      go[u] = e * QNP + q * NP + CW * w;
+      if (ok[u]) kv[u] = lds_get<V>(tile + (q * E + e) * S + CW * w);
+    }
+    if (MODE != 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ok[u]) x[u] = ld_once<NT, V>(xr + go[u]);
+    }
+    if (MODE == 2) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ok[u]) y[u] = ld_once<NT, V>(accr + go[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!ok[u]) continue;
+      V o, an;
+      rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
+      *reinterpret_cast<V *>(outr + go[u]) = o;
+      if (MODE == 1 || MODE == 2) st_once<NT, V>(accr + go[u], an);
+    }
+  }
+}
+
 // MODE: 0 writes L(f_s); 1 first RK4 stage; 2 second and third; 4 fourth.
 // One element block blk and velocity tile tile_y of the stage, by one
 // work-group; the body of the general kernel and of the batched kernel.
@@ -549,50 +646,17 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
   __syncthreads();
 
   // ---- 4. RK4 register update, coalesced over each velocity row -----------------
-  const double cacc = a.c_acc, cout = a.c_out;
-  // x: f_s (stage 1), f_n (stages 2, 3), acc (stage 4); y: acc (stages 2, 3)
-  const double *xr = (MODE == 1 ? a.fs : MODE == 2 ? a.fn : a.acc) + boff;
-  double *accr = a.acc + boff;
-  double *outr = a.out + boff;
-  for (int c0 = tid; c0 < nch; c0 += nthr * U) {
-    V kv[U], x[U], y[U];
-    size_t go[U];
-    bool ok[U];
-    const bool all = full && c0 - tid + U * nthr <= nch;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int c = c0 + u * nthr;
-      int q, e, w;
-      split_access<CPE>(c, Qb, E, q, e, w);
-      ok[u] = all || (c < nch && e < Eb);
-      go[u] = e * QNP + q * NP + CW * w;
-      if (ok[u]) kv[u] = lds_get<V>(tile + (q * E + e) * S + CW * w);
-    }
-    if (MODE != 0) {
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (ok[u]) x[u] = *reinterpret_cast<const V *>(xr + go[u]);
-    }
-    if (MODE == 2) {
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (ok[u]) y[u] = *reinterpret_cast<const V *>(accr + go[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (!ok[u]) continue;
-      V o, an;
-      rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
-      *reinterpret_cast<V *>(outr + go[u]) = o;
-      if (MODE == 1 || MODE == 2) *reinterpret_cast<V *>(accr + go[u]) = an;
-    }
-  }
+  if (a.stream_nt)
+    update_rows<P, MODE, true>(a, tile, boff, Qb, E, Eb, nch, full, tid, nthr);
+  else
+    update_rows<P, MODE, false>(a, tile, boff, Qb, E, Eb, nch, full, tid, nthr);
 }
 
 // One work-group per (element block, velocity tile); the general kernel.
 template <int P, int MODE>
 __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
-  stage_block<P, MODE>(a, xcd_block(blockIdx.x, a.nblk), blockIdx.y);
+  stage_block<P, MODE>(a, strip_block(xcd_block(blockIdx.x, a.nblk), a.nx, a.log2E, a.nblk),
+                       blockIdx.y);
 }
 
 // Batched stage over several problems of the same order P: work item i is

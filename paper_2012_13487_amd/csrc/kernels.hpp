@@ -47,6 +47,7 @@ struct StageArgs {
   int wall_mask;               // bit s: side s is a diffuse wall
   int periodic_x, periodic_y;
   int fused;                   // 1: moments and wall densities computed in-block
+  int stream_nt;               // 1: x and the accumulator move with non-temporal hints
 };
 
 // LDS bytes of the stage kernel for (p, E, Qt).

@@ -68,6 +68,30 @@ __device__ inline int xcd_block32(int b, int nblk) {
   return x * per + (x < rem ? x : rem) + (b >> 3);
 }
 
+constexpr int kStripElems32 = 16;  // elements per strip (measured best)
+
+// The t-th element block in strip order: strips of kStripElems32 elements,
+// each swept row by row, so that the work-groups resident on one XCD cover a
+// compact patch and find their neighbours' faces in L2.  Applies when the
+// blocks tile whole mesh rows (E divides nx); otherwise the identity.
+__device__ inline int strip_block32(int t, int nx, int E, int nblk) {
+  if (nx % E) return t;
+  const int W = kStripElems32 / E > 0 ? kStripElems32 / E : 1;  // blocks per strip
+  const int bpr = nx / E, rows = nblk / bpr;
+  const int full = bpr - bpr % W;
+  int row, col;
+  if (t < full * rows) {
+    const int per = W * rows, s = t / per, in = t - s * per;
+    row = in / W;
+    col = s * W + in % W;
+  } else {
+    const int wr = bpr - full, t2 = t - full * rows;
+    row = t2 / wr;
+    col = full + t2 % wr;
+  }
+  return row * bpr + col;
+}
+
 __device__ inline int neighbour32(int k, int face, const Stage32Args &a) {
   const int ex = k % a.nx, ey = k / a.nx;
   switch (face) {
@@ -144,6 +168,84 @@ __device__ __forceinline__ void volume_bf16(const float *tile, int S, int r0w, i
     if (kg == gi && own_valid) {
 #pragma unroll
       for (int n = 0; n < NP; ++n) kk[n] = -(ax * vs[n * 16 + col] + ay * vs[(NP + n) * 16 + col]);
+    }
+  }
+}
+
+// Loads and stores of the streams touched once per stage, with or without
+// non-temporal hints.
+template <bool NT, typename V>
+__device__ __forceinline__ V ld_once32(const float *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+  return *reinterpret_cast<const V *>(p);
+}
+template <bool NT, typename V>
+__device__ __forceinline__ void st_once32(float *p, const V &v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+  else *reinterpret_cast<V *>(p) = v;
+}
+
+// Phase 4 of an FP32 stage: the RK4 update of the block (contiguous floats),
+// L(g) in the LDS tile.  With NT, x and the accumulator, read once per stage
+// and not again before the next launch, move with non-temporal hints so that
+// they do not evict the tiles neighbours still gather from (used when the
+// state arrays exceed the last-level cache); the stage output, the next
+// stage's input, is always stored normally.
+template <int P, int MODE, int CW, bool NT>
+__device__ __forceinline__ void update32(const Stage32Args &a, const float *tile, size_t boff, int nch,
+                                         int tid, int nthr) {
+  using Sh = Shape32<P>;
+  constexpr int NP = Sh::NP, S = Sh::S;
+  constexpr int U = 8;
+  using V = typename std::conditional<CW == 4, float4v, float>::type;
+  const float cacc = a.c_acc, cout = a.c_out;
+  const float *xr = (MODE == 1 ? a.fs : a.fn) + boff;
+  float *accr = a.acc + boff;
+  float *outr = a.out + boff;
+  for (int c0 = tid; c0 < nch; c0 += nthr * U) {
+    V x[U], y[U];
+    if (MODE != 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * nthr;
+        if (c < nch) x[u] = ld_once32<NT, V>(xr + (size_t)c * CW);
+      }
+    }
+    if (MODE == 2 || MODE == 4) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * nthr;
+        if (c < nch) y[u] = ld_once32<NT, V>(accr + (size_t)c * CW);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * nthr;
+      if (c >= nch) continue;
+      V o, an;
+#pragma unroll
+      for (int i = 0; i < CW; ++i) {
+        const int j = c * CW + i, r = j / NP, n = j - r * NP;
+        const float kv = tile[r * S + n];
+        float xi = 0.0f, yi = 0.0f, ai = 0.0f, oi;
+        if constexpr (CW == 4) {
+          if (MODE != 0) xi = x[u][i];
+          if (MODE == 2 || MODE == 4) yi = y[u][i];
+        } else {
+          if (MODE != 0) xi = x[u];
+          if (MODE == 2 || MODE == 4) yi = y[u];
+        }
+        oi = rk32<MODE>(kv, xi, yi, cacc, cout, ai);
+        if constexpr (CW == 4) {
+          o[i] = oi;
+          an[i] = ai;
+        } else {
+          o = oi;
+          an = ai;
+        }
+      }
+      *reinterpret_cast<V *>(outr + (size_t)c * CW) = o;
+      if (MODE == 1 || MODE == 2) st_once32<NT, V>(accr + (size_t)c * CW, an);
     }
   }
 }
@@ -394,61 +496,15 @@ __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
   __syncthreads();
 
   // ---- 4. RK4 update, coalesced over the contiguous block -----------------------
-  const float cacc = a.c_acc, cout = a.c_out;
-  const float *xr = (MODE == 1 ? a.fs : a.fn) + boff;
-  float *accr = a.acc + boff;
-  float *outr = a.out + boff;
-  for (int c0 = tid; c0 < nch; c0 += nthr * U) {
-    V x[U], y[U];
-    if (MODE != 0) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int c = c0 + u * nthr;
-        if (c < nch) x[u] = *reinterpret_cast<const V *>(xr + (size_t)c * CW);
-      }
-    }
-    if (MODE == 2 || MODE == 4) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int c = c0 + u * nthr;
-        if (c < nch) y[u] = *reinterpret_cast<const V *>(accr + (size_t)c * CW);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int c = c0 + u * nthr;
-      if (c >= nch) continue;
-      V o, an;
-#pragma unroll
-      for (int i = 0; i < CW; ++i) {
-        const int j = c * CW + i, r = j / NP, n = j - r * NP;
-        const float kv = tile[r * S + n];
-        float xi = 0.0f, yi = 0.0f, ai = 0.0f, oi;
-        if constexpr (CW == 4) {
-          if (MODE != 0) xi = x[u][i];
-          if (MODE == 2 || MODE == 4) yi = y[u][i];
-        } else {
-          if (MODE != 0) xi = x[u];
-          if (MODE == 2 || MODE == 4) yi = y[u];
-        }
-        oi = rk32<MODE>(kv, xi, yi, cacc, cout, ai);
-        if constexpr (CW == 4) {
-          o[i] = oi;
-          an[i] = ai;
-        } else {
-          o = oi;
-          an = ai;
-        }
-      }
-      *reinterpret_cast<V *>(outr + (size_t)c * CW) = o;
-      if (MODE == 1 || MODE == 2) *reinterpret_cast<V *>(accr + (size_t)c * CW) = an;
-    }
-  }
+  if (a.stream_nt)
+    update32<P, MODE, CW, true>(a, tile, boff, nch, tid, nthr);
+  else
+    update32<P, MODE, CW, false>(a, tile, boff, nch, tid, nthr);
 }
 
 template <int P, int MODE, int CW, bool BF>
 __global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) {
-  stage32_block<P, MODE, CW, BF>(a, xcd_block32(blockIdx.x, a.nblk));
+  stage32_block<P, MODE, CW, BF>(a, strip_block32(xcd_block32(blockIdx.x, a.nblk), a.nx, a.E, a.nblk));
 }
 
 // Batched FP32 stage over problems of the same order P and access width CW:

@@ -38,6 +38,7 @@ struct Stage32Args {
   int stage;             // 0: out = L(f_s); 1..4: classical RK4 stage
   int wall_mask;
   int periodic_x, periodic_y;
+  int stream_nt;         // 1: x and the accumulator move with non-temporal hints
 };
 
 // Whether the bf16 matrix-core contraction variant is built for order p.
