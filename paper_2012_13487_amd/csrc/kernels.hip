@@ -542,10 +542,61 @@ __device__ __forceinline__ void update_rows(const StageArgs &a, const double *ti
   }
 }
 
+// One pass of phase 4 (U accesses per thread from c0), the same update as
+// update_rows; the velocity-tiled block loops over passes itself, a code
+// layout that measured faster there.
+template <int P, int MODE, bool NT>
+__device__ __forceinline__ void update_pass(const StageArgs &a, const double *tile, const double *xr,
+                                            double *accr, double *outr, int c0, int Qb, int E, int Eb,
+                                            int nch, bool full, int tid, int nthr) {
+  using Sh = Shape<P>;
+  constexpr int NP = Sh::NP, S = Sh::S;
+  constexpr int CW = Sh::VEC ? 2 : 1;
+  constexpr int CPE = NP / CW;
+  constexpr int U = 8;
+  using V = typename std::conditional<Sh::VEC, double2v, double>::type;
+  const size_t QNP = (size_t)a.Q * NP;
+  const double cacc = a.c_acc, cout = a.c_out;
+  V kv[U], x[U], y[U];
+  size_t go[U];
+  bool ok[U];
+  const bool all = full && c0 - tid + U * nthr <= nch;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int c = c0 + u * nthr;
+    int q, e, w;
+    split_access<CPE>(c, Qb, E, q, e, w);
+    ok[u] = all || (c < nch && e < Eb);
+    go[u] = e * QNP + q * NP + CW * w;
+    if (ok[u]) kv[u] = lds_get<V>(tile + (q * E + e) * S + CW * w);
+  }
+  if (MODE != 0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (ok[u]) x[u] = ld_once<NT, V>(xr + go[u]);
+  }
+  if (MODE == 2) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (ok[u]) y[u] = ld_once<NT, V>(accr + go[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (!ok[u]) continue;
+    V o, an;
+    rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
+    *reinterpret_cast<V *>(outr + go[u]) = o;
+    if (MODE == 1 || MODE == 2) st_once<NT, V>(accr + go[u], an);
+  }
+}
+
 // MODE: 0 writes L(f_s); 1 first RK4 stage; 2 second and third; 4 fourth.
+// FUSED: the block reduces its own moments and wall densities (a.fused).
 // One element block blk and velocity tile tile_y of the stage, by one
 // work-group; the body of the general kernel and of the batched kernel.
-template <int P, int MODE>
+// NTM: 0 the cache policy of phase 4 is chosen at run time (a.stream_nt);
+// 1 / 2 it is fixed to non-temporal / normal at compile time.
+template <int P, int MODE, bool FUSED, int NTM>
 __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int tile_y) {
   using Sh = Shape<P>;
   constexpr int NP = Sh::NP, NFP = Sh::NFP, S = Sh::S;
@@ -606,7 +657,7 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
   __syncthreads();
 
   // ---- 2. node moments and diffuse-wall densities ----------------------------
-  if (a.fused) {
+  if (FUSED) {
     block_moments_mfma<P, 16>(tile, part, a.wmom + (size_t)q0 * 16, E, Qb, Eb, tid, nthr);
     __syncthreads();
     block_moments_combine<P>(a, part, mom, rw, nbr, E, Eb, k0, tid);
@@ -646,17 +697,31 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
   __syncthreads();
 
   // ---- 4. RK4 register update, coalesced over each velocity row -----------------
-  if (a.stream_nt)
+  if constexpr (NTM != 0) {
+    const double *xr = (MODE == 1 ? a.fs : MODE == 2 ? a.fn : a.acc) + boff;
+    double *accr = a.acc + boff;
+    double *outr = a.out + boff;
+    for (int c0 = tid; c0 < nch; c0 += nthr * U)
+      update_pass<P, MODE, NTM == 1>(a, tile, xr, accr, outr, c0, Qb, E, Eb, nch, full, tid, nthr);
+  } else if (a.stream_nt) {
     update_rows<P, MODE, true>(a, tile, boff, Qb, E, Eb, nch, full, tid, nthr);
-  else
+  } else {
     update_rows<P, MODE, false>(a, tile, boff, Qb, E, Eb, nch, full, tid, nthr);
+  }
 }
 
 // One work-group per (element block, velocity tile); the general kernel.
-template <int P, int MODE>
+template <int P, int MODE, bool FUSED>
 __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
-  stage_block<P, MODE>(a, strip_block(xcd_block(blockIdx.x, a.nblk), a.nx, a.log2E, a.nblk),
-                       blockIdx.y);
+  const int blk = strip_block(xcd_block(blockIdx.x, a.nblk), a.nx, a.log2E, a.nblk);
+  // Code layouts chosen by measurement: the fused block with the run-time
+  // cache policy, the velocity-tiled block with one copy per policy.
+  if constexpr (FUSED)
+    stage_block<P, MODE, true, 0>(a, blk, blockIdx.y);
+  else if (a.stream_nt)
+    stage_block<P, MODE, false, 1>(a, blk, blockIdx.y);
+  else
+    stage_block<P, MODE, false, 2>(a, blk, blockIdx.y);
 }
 
 // Batched stage over several problems of the same order P: work item i is
@@ -681,7 +746,7 @@ __global__ __launch_bounds__(kBlock) void batch_stage_kernel(const StageArgs *de
 #else
     const StageArgs a = descs[inst];  // host pass: the body is never run on the host
 #endif
-    stage_block<P, MODE>(a, blk, 0);
+    stage_block<P, MODE, true, 0>(a, blk, 0);
     __syncthreads();  // LDS is reused by the next item
   }
 }
@@ -997,16 +1062,22 @@ __global__ void u64_to_f64_kernel(const unsigned long long *src, double *dst) {
   if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = __longlong_as_double((long long)src[0]);
 }
 
-template <int P, int MODE>
-hipError_t launch_stage_pm(const StageArgs &a, size_t lds, int ntiles, hipStream_t st) {
+template <int P, int MODE, bool FUSED>
+hipError_t launch_stage_pmf(const StageArgs &a, size_t lds, int ntiles, hipStream_t st) {
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)stage_kernel<P, MODE>,
+    hipError_t e = hipFuncSetAttribute((const void *)stage_kernel<P, MODE, FUSED>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   dim3 grid((unsigned)a.nblk, (unsigned)ntiles);
-  hipLaunchKernelGGL((stage_kernel<P, MODE>), grid, dim3(kBlock), lds, st, a);
+  hipLaunchKernelGGL((stage_kernel<P, MODE, FUSED>), grid, dim3(kBlock), lds, st, a);
   return hipGetLastError();
+}
+
+template <int P, int MODE>
+hipError_t launch_stage_pm(const StageArgs &a, size_t lds, int ntiles, hipStream_t st) {
+  return a.fused ? launch_stage_pmf<P, MODE, true>(a, lds, ntiles, st)
+                 : launch_stage_pmf<P, MODE, false>(a, lds, ntiles, st);
 }
 
 
