@@ -278,7 +278,9 @@ typedef struct {
   int32_t max_newton;   /* Newton iterations per stage (1..1000)          */
   double newton_rtol;   /* >= 0                                           */
   double newton_atol;   /* >= 0                                           */
-  int32_t restart;      /* GMRES restart length m (1..64)                 */
+  int32_t restart;      /* longest GMRES cycle m (1..64); cycles start at
+                           min(8, m) iterations and double, up to m, after
+                           a cycle that reduces the residual by < 10%      */
   int32_t max_krylov;   /* GMRES iterations per Newton step (>= 1)        */
   double krylov_rtol;   /* in (0, 1)                                      */
 } dgbgk_implicit_options;

@@ -1137,6 +1137,12 @@ bool sdirk_tableau(int scheme, Sdirk &t) {
 // quadratic equilibrium.
 constexpr double kFdStep = 1e-6;
 
+// First GMRES cycle length.  On the 64x64 p = 3 cavity the Krylov iteration
+// count barely depends on the cycle length between 3 and 45 at moderate
+// steps, while each iteration's Gram-Schmidt traffic grows with it; at very
+// large steps short cycles stagnate, hence the doubling in gmres().
+constexpr int kShortCycle = 8;
+
 // Device workspace of one implicit step, in doubles: the stage rates, the
 // Newton vectors, the Krylov basis and the small reduction buffers.
 struct ImplicitWs {
@@ -1206,6 +1212,9 @@ struct Implicit {
     int rc = check(launch_lincomb(n, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, w.X, s->stream), "zero");
     if (rc) return rc;
     double beta = fnorm2;
+    // cycle length: short cycles while they make progress, doubled (up to
+    // m) after a cycle that reduces the residual by less than 10%
+    int mc = std::min(kShortCycle, m);
     rc = check(launch_lincomb(n, -1.0 / beta, w.F, 0.0, nullptr, 0.0, nullptr, Vk(0), s->stream),
                "lincomb");
     if (rc) return rc;
@@ -1214,7 +1223,8 @@ struct Implicit {
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = beta;
       int jn = 0;
-      for (int j = 0; j < m; ++j) {
+      const double beta_cycle = beta;
+      for (int j = 0; j < mc; ++j) {
         double *v1 = Vk(j + 1);
         if ((rc = apply(Vk(j), 1.0, Ly, v1))) return rc;
         // Classical Gram-Schmidt, repeated only when the first pass cancels
@@ -1308,6 +1318,7 @@ struct Implicit {
       beta = std::sqrt(r2);
       if (!std::isfinite(beta)) return fail(s, DGBGK_ENONFINITE, "GMRES residual is not finite");
       if (beta <= tol2) break;
+      if (beta > 0.9 * beta_cycle) mc = std::min(2 * mc, m);
       if ((rc = check(launch_lincomb(n, 1.0 / beta, Vk(0), 0.0, nullptr, 0.0, nullptr, Vk(0), s->stream),
                       "lincomb")))
         return rc;
