@@ -168,11 +168,17 @@ int validate(const dgbgk_problem *pb, dgbgk_solver *s) {
 
 // FP32 precisions: always the fused form; E elements per work-group while
 // the tile stays within 64 KB of LDS (at least one element, up to 160 KB).
+// Largest block, in DOF, the automatic choice gives one work-group (32 KB
+// of FP64 state): on the 64x64 p = 3 NC 16x16 cavity one element per
+// work-group (4096 DOF) measured faster than two once element blocks run in
+// strips (126 vs 129 us FP64, 68.5 vs 69.5 us FP32).
+constexpr int64_t kMaxBlockDof = 4096;
+
 void choose_tiling32(dgbgk_solver *s) {
   const int NP = s->Np;
   const bool bf = s->prec == DGBGK_FP32_BF16MMA;
   int E = 1;
-  while ((int64_t)E * 2 * s->Q * NP <= 8192 && E * 2 <= s->K &&
+  while ((int64_t)E * 2 * s->Q * NP <= kMaxBlockDof && E * 2 <= s->K &&
          stage32_lds_bytes(s->p, E * 2, s->Q, bf) <= kFusedLdsLimit)
     E *= 2;
   if (s->forced_E > 0) E = s->forced_E;
@@ -199,7 +205,7 @@ void choose_tiling(dgbgk_solver *s) {
   int E = 1;
   // the persistent kernel takes one velocity row per thread
   const bool row_cap = s->tiling_mode == 4 && s->p <= kStreamMaxP;
-  while (E * 2 <= G && (int64_t)E * 2 * s->Q * NP <= 8192 && E * 2 <= s->K &&
+  while (E * 2 <= G && (int64_t)E * 2 * s->Q * NP <= kMaxBlockDof && E * 2 <= s->K &&
          (!row_cap || (int64_t)E * 2 * s->Q <= kBlock) &&
          stage_lds_bytes(s->p, E * 2, s->Q) <= kFusedLdsLimit)
     E *= 2;

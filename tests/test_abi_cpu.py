@@ -61,8 +61,8 @@ def test_reference_element_matches_oracle(oracle_mod, p):
 def test_tiling_choice():
     s = binding.Solver.from_spec(workloads.CAVITY_64x64_P3_NC16)
     t = s.tiling()
-    # two elements of 256 velocities per work-group (78.6 KB of LDS, two per CU)
-    assert t["fused"] and t["elems_per_group"] == 2 and t["velocities_per_tile"] == 256
+    # one element of 256 velocities per work-group (41 KB of LDS)
+    assert t["fused"] and t["elems_per_group"] == 1 and t["velocities_per_tile"] == 256
     assert not t["persistent"] and t["lds_bytes"] <= 80 * 1024
     big = binding.Solver.from_spec(workloads.CAVITY_128x128_P4_NC24_KN8)
     t = big.tiling()
