@@ -57,6 +57,8 @@ RHS_CASES = [
     ("cavity_9x7_p3_nc9", workloads.cavity(n=9, ny=7, p=3, m=9, lid=0.15)),
     ("cavity_3x2_p6_nc4", workloads.cavity(n=3, ny=2, p=6, m=4)),
     ("collisionless_4x4_p3", workloads.periodic_box(nx=4, ny=4, p=3, tau=float("inf"))),
+    # strip-ordered blocks: one element per block (20 columns, strips of 16)
+    ("cavity_20x3_p2_nc16_strips", workloads.cavity(n=20, ny=3, p=2, m=16, lid=0.1)),
 ]
 
 

@@ -54,6 +54,10 @@ RHS_CASES = [
     ("cavity_9x7_p3_nc9_persistent", workloads.cavity(n=9, ny=7, p=3, m=9, lid=0.15), (4, 0)),
     ("couette_8x8_p2_gh4_persistent", workloads.couette(nx=8, ny=8, p=2), (4, 0)),
     ("collisionless_4x4_p3", workloads.periodic_box(nx=4, ny=4, p=3, tau=float("inf")), None),
+    # strip-ordered blocks with full strips and a narrower last strip:
+    # one element per block (20 columns, strips of 16), two (20 blocks of 2, strips of 8)
+    ("cavity_20x3_p2_nc16_strips_E1", workloads.cavity(n=20, ny=3, p=2, m=16, lid=0.1), None),
+    ("cavity_40x2_p3_nc10_strips_E2", workloads.cavity(n=40, ny=2, p=3, m=10, lid=0.1), None),
 ]
 
 
@@ -98,6 +102,22 @@ def test_couette_200_steps_matches_oracle(oracle_mod):
     rho, ux, uy = g.moments()
     assert np.max(np.abs(rho - 1)) < 1e-13 and np.max(np.abs(uy)) < 1e-14
     assert g.steps_taken() == spec.steps
+
+
+@pytest.mark.parametrize("name,spec,tiling", RHS_CASES[-2:], ids=[c[0] for c in RHS_CASES[-2:]])
+def test_strip_ordered_blocks_steps_match_oracle(oracle_mod, name, spec, tiling):
+    _say(f"[gpu] strip-ordered blocks, 20 steps: {name}")
+    g, o = _pair(oracle_mod, spec, tiling)
+    assert g.tiling()["elems_per_group"] == (1 if "E1" in name else 2)
+    f = workloads.perturbed_state(29, o.w, o.K, o.Np, amp=0.05)
+    g.set_state(f)
+    o.set_state(f)
+    dt = o.stable_dt(0.2)
+    g.step(20, dt)
+    o.rk4(20, dt)
+    er, eu = _moment_errors(g, o)
+    assert er < TOL and eu < TOL, (er, eu)
+    assert _rel(g.get_state(), o.get_state()) < TOL
 
 
 @pytest.mark.parametrize("tiling", [None, (2, 13), (4, 0)])
