@@ -596,7 +596,8 @@ __device__ __forceinline__ void update_pass(const StageArgs &a, const double *ti
 // work-group; the body of the general kernel and of the batched kernel.
 // NTM: 0 the cache policy of phase 4 is chosen at run time (a.stream_nt);
 // 1 / 2 it is fixed to non-temporal / normal at compile time.
-template <int P, int MODE, bool FUSED, int NTM>
+// EFIX: elements per work-group fixed at compile time (0: a.E at run time).
+template <int P, int MODE, bool FUSED, int NTM, int EFIX = 0>
 __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int tile_y) {
   using Sh = Shape<P>;
   constexpr int NP = Sh::NP, NFP = Sh::NFP, S = Sh::S;
@@ -607,7 +608,7 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
   constexpr int U = FUSED ? 8 : 16;
   using V = typename std::conditional<Sh::VEC, double2v, double>::type;
   extern __shared__ double lds[];
-  const int E = a.E, log2E = a.log2E;
+  const int E = EFIX > 0 ? EFIX : a.E, log2E = EFIX == 1 ? 0 : a.log2E;
   const LdsLayout L = lds_layout(NP, NFP, S, E, a.Qt);
   double *tile = lds;
   double *part = lds + L.part;
@@ -713,12 +714,15 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
 }
 
 // One work-group per (element block, velocity tile); the general kernel.
-template <int P, int MODE, bool FUSED>
+// FK: 0 velocity-tiled blocks, 1 fused blocks, 2 fused blocks of one element.
+template <int P, int MODE, int FK>
 __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
   const int blk = strip_block(xcd_block(blockIdx.x, a.nblk), a.nx, a.log2E, a.nblk);
   // Code layouts chosen by measurement: the fused block with the run-time
   // cache policy, the velocity-tiled block with one copy per policy.
-  if constexpr (FUSED)
+  if constexpr (FK == 2)
+    stage_block<P, MODE, true, 0, 1>(a, blk, blockIdx.y);
+  else if constexpr (FK == 1)
     stage_block<P, MODE, true, 0>(a, blk, blockIdx.y);
   else if (a.stream_nt)
     stage_block<P, MODE, false, 1>(a, blk, blockIdx.y);
@@ -1064,22 +1068,23 @@ __global__ void u64_to_f64_kernel(const unsigned long long *src, double *dst) {
   if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = __longlong_as_double((long long)src[0]);
 }
 
-template <int P, int MODE, bool FUSED>
+template <int P, int MODE, int FK>
 hipError_t launch_stage_pmf(const StageArgs &a, size_t lds, int ntiles, hipStream_t st) {
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)stage_kernel<P, MODE, FUSED>,
+    hipError_t e = hipFuncSetAttribute((const void *)stage_kernel<P, MODE, FK>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   dim3 grid((unsigned)a.nblk, (unsigned)ntiles);
-  hipLaunchKernelGGL((stage_kernel<P, MODE, FUSED>), grid, dim3(kBlock), lds, st, a);
+  hipLaunchKernelGGL((stage_kernel<P, MODE, FK>), grid, dim3(kBlock), lds, st, a);
   return hipGetLastError();
 }
 
 template <int P, int MODE>
 hipError_t launch_stage_pm(const StageArgs &a, size_t lds, int ntiles, hipStream_t st) {
-  return a.fused ? launch_stage_pmf<P, MODE, true>(a, lds, ntiles, st)
-                 : launch_stage_pmf<P, MODE, false>(a, lds, ntiles, st);
+  if (!a.fused) return launch_stage_pmf<P, MODE, 0>(a, lds, ntiles, st);
+  return a.E == 1 ? launch_stage_pmf<P, MODE, 2>(a, lds, ntiles, st)
+                  : launch_stage_pmf<P, MODE, 1>(a, lds, ntiles, st);
 }
 
 

@@ -253,14 +253,16 @@ __device__ __forceinline__ void update32(const Stage32Args &a, const float *tile
 // MODE: 0 writes L(f_s); 1 first RK4 stage; 2 second and third; 4 fourth.
 // CW: floats per global access (4 when Q Np is a multiple of 4, else 1).
 // BF: the volume term's contractions Dr g, Ds g on bf16 matrix cores.
-template <int P, int MODE, int CW, bool BF>
+// EFIX: elements per work-group fixed at compile time (0: a.E at run time);
+// the one-element form drops the block's index arithmetic.
+template <int P, int MODE, int CW, bool BF, int EFIX = 0>
 __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
   using Sh = Shape32<P>;
   constexpr int N1 = Sh::N1, NP = Sh::NP, NFP = Sh::NFP, S = Sh::S, NB = Sh::NB;
   constexpr int U = 8;  // global accesses in flight per thread
   using V = typename std::conditional<CW == 4, float4v, float>::type;
   extern __shared__ double lds[];
-  const int E = a.E, Q = a.Q;
+  const int E = EFIX > 0 ? EFIX : a.E, Q = a.Q;
   const Lds32 L = lds32_layout(NP, NFP, S, E, Q, BF);
   float *tile = (float *)lds;
   double *part = lds + L.part;
@@ -502,9 +504,10 @@ __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
     update32<P, MODE, CW, false>(a, tile, boff, nch, tid, nthr);
 }
 
-template <int P, int MODE, int CW, bool BF>
+template <int P, int MODE, int CW, bool BF, int EFIX>
 __global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) {
-  stage32_block<P, MODE, CW, BF>(a, strip_block32(xcd_block32(blockIdx.x, a.nblk), a.nx, a.E, a.nblk));
+  stage32_block<P, MODE, CW, BF, EFIX>(
+      a, strip_block32(xcd_block32(blockIdx.x, a.nblk), a.nx, EFIX > 0 ? EFIX : a.E, a.nblk));
 }
 
 // Batched FP32 stage over problems of the same order P and access width CW:
@@ -644,16 +647,23 @@ hipError_t launch_batch32_pb(int stage, int cw, const Stage32Args *descs, const 
   return launch_batch32_pcb<P, 1, BF>(stage, descs, items, nitems, lds, groups, st);
 }
 
-template <int P, int MODE, int CW, bool BF>
-hipError_t launch32_pmcb(const Stage32Args &a, size_t lds, hipStream_t st) {
+template <int P, int MODE, int CW, bool BF, int EFIX>
+hipError_t launch32_pmcbe(const Stage32Args &a, size_t lds, hipStream_t st) {
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)stage32_kernel<P, MODE, CW, BF>,
+    hipError_t e = hipFuncSetAttribute((const void *)stage32_kernel<P, MODE, CW, BF, EFIX>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((stage32_kernel<P, MODE, CW, BF>), dim3((unsigned)a.nblk), dim3(kBlock32), lds,
-                     st, a);
+  hipLaunchKernelGGL((stage32_kernel<P, MODE, CW, BF, EFIX>), dim3((unsigned)a.nblk), dim3(kBlock32),
+                     lds, st, a);
   return hipGetLastError();
+}
+
+template <int P, int MODE, int CW, bool BF>
+hipError_t launch32_pmcb(const Stage32Args &a, size_t lds, hipStream_t st) {
+  if constexpr (P <= 4)
+    if (a.E == 1) return launch32_pmcbe<P, MODE, CW, BF, 1>(a, lds, st);
+  return launch32_pmcbe<P, MODE, CW, BF, 0>(a, lds, st);
 }
 
 template <int P, int MODE, bool BF>
