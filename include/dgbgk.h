@@ -312,8 +312,11 @@ int dgbgk_implicit_step(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double 
  * them.  Each member's result is bit-identical to stepping it alone with the
  * same work decomposition (batch invariance).  Members use the fused form (all
  * velocities of a block of elements per work-group); a member whose fused tile
- * does not fit in LDS is rejected (DGBGK_ENOTSUP).  The solvers must outlive
- * the batch. */
+ * does not fit in LDS is rejected (DGBGK_ENOTSUP).  The members' launch
+ * configuration (dgbgk_set_tiling, dgbgk_set_block_elements, dgbgk_autotune)
+ * is read when the batch is built and must not change while they are in it
+ * (dgbgk_batch_step returns DGBGK_ESTATE).  The solvers must outlive the
+ * batch. */
 typedef struct dgbgk_batch dgbgk_batch;
 
 /* Builds work lists and descriptor tables on the device (the members' device

@@ -1482,6 +1482,7 @@ struct dgbgk_batch {
   char *dev = nullptr;
   std::vector<char> host;          // staging of the descriptor tables
   std::vector<double> dt_loaded;   // dt each member's descriptors hold (NaN: none)
+  std::vector<int> E_built;        // each member's elements per block when the lists were built
   bool use_graph = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1695,6 +1696,8 @@ int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream
     b->own_stream = true;
   }
   b->dt_loaded.assign(n, std::nan(""));
+  b->E_built.resize(n);
+  for (int i = 0; i < n; ++i) b->E_built[i] = b->s[i]->E;
   fill_descriptors(b, nullptr);
   if ((rc = upload_descriptors(b))) {
     const std::string msg = b->err;
@@ -1719,6 +1722,8 @@ int dgbgk_batch_step(dgbgk_batch *b, int64_t nsteps, const double *dt) {
   for (size_t i = 0; i < n; ++i) {
     if (!(dt[i] > 0) || !std::isfinite(dt[i])) return bfail(b, DGBGK_EINVAL, "dt[%zu] must be > 0", i);
     if (!b->s[i]->have_state) return bfail(b, DGBGK_ESTATE, "member %zu has no state", i);
+    if (b->s[i]->E != b->E_built[i] || !b->s[i]->fused)
+      return bfail(b, DGBGK_ESTATE, "member %zu was re-tiled after the batch was built", i);
   }
   bool changed = false;
   for (size_t i = 0; i < n; ++i) changed |= !(b->dt_loaded[i] == dt[i]);

@@ -114,6 +114,13 @@ def test_batch_rejects_unfit_member_and_needs_state():
     assert ei.value.code == binding.EINVAL
     b.step(2, [g.stable_dt(0.2)])
     assert g.steps_taken() == 2
+    # re-tiling a member after the batch was built is refused
+    e0 = g.tiling()["elems_per_group"]
+    g.set_block_elements(1 if e0 != 1 else 2)
+    with pytest.raises(binding.DgbgkError) as ei:
+        b.step(1, [g.stable_dt(0.2)])
+    assert ei.value.code == binding.ESTATE
+    assert g.steps_taken() == 2
     b.close()
 
 
