@@ -724,7 +724,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
     stage_block<P, MODE, true, 0, 1>(a, blk, blockIdx.y);
   else if constexpr (FK == 1)
     stage_block<P, MODE, true, 0>(a, blk, blockIdx.y);
-  else if (a.stream_nt)
+  else if (a.stream_nt)  // (velocity tiles hold one element, but the run-time E measured faster)
     stage_block<P, MODE, false, 1>(a, blk, blockIdx.y);
   else
     stage_block<P, MODE, false, 2>(a, blk, blockIdx.y);
@@ -1082,7 +1082,10 @@ hipError_t launch_stage_pmf(const StageArgs &a, size_t lds, int ntiles, hipStrea
 
 template <int P, int MODE>
 hipError_t launch_stage_pm(const StageArgs &a, size_t lds, int ntiles, hipStream_t st) {
-  if (!a.fused) return launch_stage_pmf<P, MODE, 0>(a, lds, ntiles, st);
+  if (!a.fused) {
+    if (a.E != 1) return hipErrorInvalidValue;  // velocity tiles hold one element
+    return launch_stage_pmf<P, MODE, 0>(a, lds, ntiles, st);
+  }
   return a.E == 1 ? launch_stage_pmf<P, MODE, 2>(a, lds, ntiles, st)
                   : launch_stage_pmf<P, MODE, 1>(a, lds, ntiles, st);
 }
