@@ -150,16 +150,13 @@ def batching(steps):
             g.init_equilibrium()
         tuned = {}
         if batched:
-            # the autotuner, once per (precision, p, Q) class; members of a
-            # batch run the fused form
-            for g, sp in zip(solvers, specs):
-                key = (g.p, g.Q)
-                g.set_tiling(1)
-                if key not in tuned:
-                    g.autotune(3)
-                    tuned[key] = g.tiling()["elems_per_group"]
-                else:
-                    g.set_block_elements(tuned[key])
+            # the autotuner on every member (fused blocks of each admissible
+            # size and, in FP64, velocity tiles); the batch keeps the choice of
+            # members large enough to run their own kernels and gives the
+            # others the fused form
+            for g in solvers:
+                g.autotune(3)
+                tuned[(g.p, g.Q)] = g.tiling()["elems_per_group"]
         dts = np.array([g.stable_dt(sp.cfl) for g, sp in zip(solvers, specs)])
         dof = sum(g.ndof for g in solvers)
         if batched:

@@ -307,12 +307,15 @@ int dgbgk_implicit_step(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double 
  * launch per class of (precision, order p, access width, LDS size) that walks
  * a device work list of (problem, element block) items and reads each
  * problem's arguments (state pointers, mesh and velocity tables, tau, walls,
- * and its own dt) from a device descriptor table.  The members keep their own
+ * and its own dt) from a device descriptor table.  A member of 2^22 DOF
+ * (K Np Q) or more fills the GPU by itself and runs its own single-problem
+ * stage kernels, in its own decomposition, in the same step instead (with such
+ * members a change of dt re-captures the step graph).  The members keep their own
  * device memory and states; while they are in a batch, use the batch to step
  * them.  Each member's result is bit-identical to stepping it alone with the
- * same work decomposition (batch invariance).  Members use the fused form (all
- * velocities of a block of elements per work-group); a member whose fused tile
- * does not fit in LDS is rejected (DGBGK_ENOTSUP).  The members' launch
+ * same work decomposition (batch invariance).  Smaller members use the fused form (all
+ * velocities of a block of elements per work-group); a smaller member whose
+ * fused tile does not fit in LDS is rejected (DGBGK_ENOTSUP).  The members' launch
  * configuration (dgbgk_set_tiling, dgbgk_set_block_elements, dgbgk_autotune)
  * is read when the batch is built and must not change while they are in it
  * (dgbgk_batch_step returns DGBGK_ESTATE).  The solvers must outlive the

@@ -68,6 +68,11 @@ Layout make_layout(int64_t K, int Np, int Nfp, int Q, int precision) {
 
 thread_local std::string g_create_error;
 
+// Size (DOF) from which a batch member runs its own single-problem stage
+// kernels, in its own decomposition, instead of joining a persistent class
+// launch: 2^22 DOF fill the GPU with 1024 or more work-groups.
+constexpr int64_t kSoloDof = (int64_t)1 << 22;
+
 }  // namespace
 
 struct dgbgk_solver {
@@ -1479,10 +1484,12 @@ struct dgbgk_batch {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::vector<Class> cls;
+  std::vector<int> solo;           // members large enough to run their own stage kernels
   char *dev = nullptr;
   std::vector<char> host;          // staging of the descriptor tables
   std::vector<double> dt_loaded;   // dt each member's descriptors hold (NaN: none)
   std::vector<int> E_built;        // each member's elements per block when the lists were built
+  std::vector<int> fused_built;    // and its fused flag
   bool use_graph = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1582,12 +1589,33 @@ int launch_class(dgbgk_batch *b, const dgbgk_batch::Class &c, int stage) {
   return DGBGK_OK;
 }
 
+// A member of kSoloDof or more fills the GPU on its own: the batch launches
+// its single-problem stage kernels, in its own decomposition (same results as
+// stepping it alone), and packs only the smaller members into the persistent
+// kernels, which pay off where launches dominate.
+int launch_solo(dgbgk_batch *b, int i, int stage) {
+  dgbgk_solver *s = b->s[i];
+  void *fs, *out;
+  stage_buffers(s, stage, fs, out);
+  hipStream_t own = s->stream;
+  s->stream = b->stream;
+  const int rc = run_stage(s, stage, fs, out, b->dt_loaded[i]);
+  s->stream = own;
+  if (rc) return bfail(b, rc, "member %d: %s", i, s->err.c_str());
+  return DGBGK_OK;
+}
+
 int enqueue_step(dgbgk_batch *b) {
-  for (int stage = 1; stage <= 4; ++stage)
+  for (int stage = 1; stage <= 4; ++stage) {
     for (const auto &c : b->cls) {
       int rc = launch_class(b, c, stage);
       if (rc) return rc;
     }
+    for (int i : b->solo) {
+      int rc = launch_solo(b, i, stage);
+      if (rc) return rc;
+    }
+  }
   return DGBGK_OK;
 }
 
@@ -1619,6 +1647,11 @@ int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream
   int rc = DGBGK_OK;
   for (int i = 0; i < n && !rc; ++i) {
     dgbgk_solver *s = b->s[i];
+    if ((int64_t)s->K * s->Np * s->Q >= kSoloDof) {  // keeps its own decomposition
+      b->solo.push_back(i);
+      if ((rc = ensure_device(s))) bfail(nullptr, rc, "solver %d: %s", i, s->err.c_str());
+      continue;
+    }
     if (!s->fused || s->persistent) {  // members run the fused per-block body
       s->tiling_mode = 1;
       choose_tiling(s);
@@ -1636,6 +1669,7 @@ int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream
   const size_t bins[4] = {40 * 1024, 64 * 1024, 80 * 1024, 160 * 1024};
   for (int i = 0; i < n; ++i) {
     dgbgk_solver *s = b->s[i];
+    if (std::find(b->solo.begin(), b->solo.end(), i) != b->solo.end()) continue;
     const bool f32 = is_fp32(s->prec);
     const int cw = f32 ? (((int64_t)s->Q * s->Np) % 4 == 0 ? 4 : 1) : 0;
     const int contract = s->prec == DGBGK_FP32_BF16MMA;
@@ -1680,7 +1714,7 @@ int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream
   b->host.assign(off, 0);
   for (auto &c : b->cls)
     std::memcpy(b->host.data() + c.off_items, c.items.data(), c.items.size() * sizeof(int2));
-  hipError_t e = hipMalloc((void **)&b->dev, off);
+  hipError_t e = hipMalloc((void **)&b->dev, std::max<size_t>(off, kAlign));  // all members solo: off = 0
   if (e != hipSuccess) {
     delete b;
     return bfail(nullptr, DGBGK_ENOMEM, "hipMalloc(%zu): %s", off, hipGetErrorString(e));
@@ -1697,7 +1731,11 @@ int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream
   }
   b->dt_loaded.assign(n, std::nan(""));
   b->E_built.resize(n);
-  for (int i = 0; i < n; ++i) b->E_built[i] = b->s[i]->E;
+  b->fused_built.resize(n);
+  for (int i = 0; i < n; ++i) {
+    b->E_built[i] = b->s[i]->E;
+    b->fused_built[i] = b->s[i]->fused;
+  }
   fill_descriptors(b, nullptr);
   if ((rc = upload_descriptors(b))) {
     const std::string msg = b->err;
@@ -1722,7 +1760,7 @@ int dgbgk_batch_step(dgbgk_batch *b, int64_t nsteps, const double *dt) {
   for (size_t i = 0; i < n; ++i) {
     if (!(dt[i] > 0) || !std::isfinite(dt[i])) return bfail(b, DGBGK_EINVAL, "dt[%zu] must be > 0", i);
     if (!b->s[i]->have_state) return bfail(b, DGBGK_ESTATE, "member %zu has no state", i);
-    if (b->s[i]->E != b->E_built[i] || !b->s[i]->fused)
+    if (b->s[i]->E != b->E_built[i] || b->s[i]->fused != b->fused_built[i])
       return bfail(b, DGBGK_ESTATE, "member %zu was re-tiled after the batch was built", i);
   }
   bool changed = false;
@@ -1735,6 +1773,8 @@ int dgbgk_batch_step(dgbgk_batch *b, int64_t nsteps, const double *dt) {
     fill_descriptors(b, dt);
     if ((rc = upload_descriptors(b))) return rc;
     for (size_t i = 0; i < n; ++i) b->dt_loaded[i] = dt[i];
+    // the single-problem launches of large members carry dt in their arguments
+    if (!b->solo.empty()) drop_graph(b);
   }
   if (nsteps == 0) return DGBGK_OK;
   if (b->use_graph && !b->exec) {
@@ -1807,7 +1847,7 @@ int dgbgk_batch_residuals(dgbgk_batch *b, double *r) {
 int dgbgk_batch_launches_per_step(const dgbgk_batch *b, int32_t *launches) {
   if (!b) return bfail(nullptr, DGBGK_EINVAL, "batch is NULL");
   if (!launches) return bfail(const_cast<dgbgk_batch *>(b), DGBGK_EINVAL, "launches is NULL");
-  *launches = (int32_t)(4 * b->cls.size());
+  *launches = (int32_t)(4 * (b->cls.size() + b->solo.size()));
   return DGBGK_OK;
 }
 
