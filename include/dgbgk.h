@@ -166,6 +166,14 @@ int dgbgk_get_operator(const dgbgk_solver *s, int32_t which, double *out);
 /* f_q = f_q^eq(rho0, (ux0, uy0)) at every node (eq. (5)). */
 int dgbgk_init_equilibrium(dgbgk_solver *s, double rho0, double ux0, double uy0);
 
+/* State f_q = f^eq_q(rho, u) of eq. (5) with each node's own density and
+ * velocity (Sec. II.A): rho, ux, uy are host arrays of K Np doubles in node
+ * order k Np + n (element k = ex + nx ey; node n = i + (p+1) j), copied before
+ * the call returns.  DGBGK_EINVAL unless count == K Np, every rho > 0 and
+ * every value finite.  Resets the step count; synchronises. */
+int dgbgk_init_moments(dgbgk_solver *s, const double *rho, const double *ux, const double *uy,
+                       size_t count);
+
 /* Copy a full FP64 state f[q][k][n] (count = Q*K*Np doubles) in / out. */
 int dgbgk_set_state(dgbgk_solver *s, const double *f, size_t count);
 int dgbgk_get_state(dgbgk_solver *s, double *f, size_t count);

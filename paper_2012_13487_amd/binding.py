@@ -97,6 +97,7 @@ SIGNATURES = {
     "dgbgk_node_coords": (C.c_int, [C.c_void_p, _dp, _dp]),
     "dgbgk_get_operator": (C.c_int, [C.c_void_p, C.c_int32, _dp]),
     "dgbgk_init_equilibrium": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double]),
+    "dgbgk_init_moments": (C.c_int, [C.c_void_p, _dp, _dp, _dp, C.c_size_t]),
     "dgbgk_set_state": (C.c_int, [C.c_void_p, _dp, C.c_size_t]),
     "dgbgk_get_state": (C.c_int, [C.c_void_p, _dp, C.c_size_t]),
     "dgbgk_state_device_ptr": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -341,6 +342,11 @@ class Solver:
                 "lds_bytes": lds.value}
 
     # -- device work
+    def init_moments(self, rho, ux, uy):
+        """f = f^eq(rho, u) node by node; arrays of shape (K, Np) or K*Np."""
+        arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in (rho, ux, uy)]
+        self._call("dgbgk_init_moments", _p(arrs[0]), _p(arrs[1]), _p(arrs[2]), arrs[0].size)
+
     def init_equilibrium(self, rho0=1.0, ux0=0.0, uy0=0.0):
         self._call("dgbgk_init_equilibrium", rho0, ux0, uy0)
 

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgbgk.so")
-SOURCES = ["dgbgk_api.hip", "kernels.hip", "kernels32.hip", "linalg.hip", "host_math.cpp", "server.cpp"]
+SOURCES = ["dgbgk_api.hip", "kernels.hip", "kernels32.hip", "linalg.hip", "init.hip", "host_math.cpp", "server.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

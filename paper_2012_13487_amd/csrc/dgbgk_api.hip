@@ -16,6 +16,7 @@
 #include "dgbgk.h"
 #include "host_math.hpp"
 #include "kernels.hpp"
+#include "init.hpp"
 #include "kernels32.hpp"
 #include "linalg.hpp"
 
@@ -753,6 +754,34 @@ int dgbgk_init_equilibrium(dgbgk_solver *s, double rho0, double ux0, double uy0)
                                       s->pb.theta, s->rho_ref, s->stream)
           : launch_init_equilibrium(s->d_fn, s->d_vel, (int)s->K, s->Np, s->Q, rho0, ux0, uy0,
                                     s->pb.theta, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "init kernel");
+  s->have_state = true;
+  s->steps = 0;
+  return DGBGK_OK;
+}
+
+int dgbgk_init_moments(dgbgk_solver *s, const double *rho, const double *ux, const double *uy,
+                       size_t count) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  const size_t KN = (size_t)s->K * s->Np;
+  if (!rho || !ux || !uy || count != KN) return fail(s, DGBGK_EINVAL, "arrays need %zu doubles", KN);
+  for (size_t i = 0; i < KN; ++i)
+    if (!(rho[i] > 0) || !is_finite_d(rho[i]) || !is_finite_d(ux[i]) || !is_finite_d(uy[i]))
+      return fail(s, DGBGK_EINVAL, "node %zu: rho must be > 0 and u finite", i);
+  int rc = ensure_device(s);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(s->d_mom, rho, KN * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_mom + KN, ux, KN * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_mom + 2 * KN, uy, KN * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "moments copy");
+  e = is_fp32(s->prec)
+          ? launch_init_moments32(s->g_fn, s->d_vel, s->d_mom, (int)s->K, s->Np, s->Q, s->pb.theta,
+                                  s->rho_ref, s->stream)
+          : launch_init_moments(s->d_fn, s->d_vel, s->d_mom, (int)s->K, s->Np, s->Q, s->pb.theta,
+                                s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // the host arrays may go away
   if (e != hipSuccess) return hip_fail(s, e, "init kernel");
   s->have_state = true;
   s->steps = 0;

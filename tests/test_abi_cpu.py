@@ -151,6 +151,21 @@ def test_bad_velocity_set_arguments():
     assert binding.tau_from_kn(1.0, 1.0, 0) == pytest.approx(1 / math.sqrt(3), rel=1e-15)
 
 
+def test_init_moments_validation():
+    s = binding.Solver.from_spec(workloads.couette(nx=2, ny=2, p=1))
+    shape = (s.K, s.Np)
+    one, zero = np.ones(shape), np.zeros(shape)
+    bad_rho = one.copy()
+    bad_rho[1, 2] = 0.0
+    bad_u = zero.copy()
+    bad_u[0, 0] = np.nan
+    for args in [(bad_rho, zero, zero), (one, bad_u, zero), (one, zero, np.full(shape, np.inf)),
+                 (np.ones(s.K * s.Np - 1), np.zeros(s.K * s.Np - 1), np.zeros(s.K * s.Np - 1))]:
+        with pytest.raises(binding.DgbgkError) as ei:
+            s.init_moments(*args)
+        assert ei.value.code == binding.EINVAL
+
+
 def test_null_handle_is_einval():
     L = binding.lib()
     assert L.dgbgk_step(None, 1, 0.1) == binding.EINVAL
@@ -168,6 +183,10 @@ def test_device_calls_fail_loudly_without_gpu():
     s = binding.Solver.from_spec(workloads.couette(nx=2, ny=2, p=1))
     with pytest.raises(binding.DgbgkError) as ei:
         s.init_equilibrium()
+    assert ei.value.code == binding.EDEVICE
+    shape = (s.K, s.Np)
+    with pytest.raises(binding.DgbgkError) as ei:
+        s.init_moments(np.ones(shape), np.zeros(shape), np.zeros(shape))
     assert ei.value.code == binding.EDEVICE
     with pytest.raises(binding.DgbgkError) as ei:
         s.step(1, 1e-3)

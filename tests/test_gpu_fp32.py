@@ -105,6 +105,25 @@ def test_fp32_state_round_trip_and_moments(oracle_mod):
     assert er < 1e-8 and eu < 1e-6
 
 
+def test_fp32_init_moments(oracle_mod):
+    _say("[gpu] fp32 init_moments")
+    spec = workloads.cavity(n=6, p=2, m=8, lid=0.1)
+    g, o = _pair(oracle_mod, spec)
+    x, y = g.node_coords()
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * x) * np.cos(np.pi * y)
+    ux, uy = 0.1 * np.cos(2 * np.pi * y), -0.08 * np.sin(2 * np.pi * x)
+    g.init_moments(rho, ux, uy)
+    want = np.empty(o.shape)
+    for k in range(o.K):
+        for n in range(o.Np):
+            want[:, k, n] = o.equilibrium(rho[k, n], ux[k, n], uy[k, n])
+    # deviation from w rho_ref stored in FP32: one rounding of a value below |f|
+    assert _rel(g.get_state(), want) < 2 ** -23
+    o.set_state(want)
+    er, eu = _moment_errors(g.moments(), o.moments())
+    assert er < TOL32 and eu < TOL32
+
+
 def test_fp32_couette_200_steps(oracle_mod):
     _say("[gpu] fp32 couette 8x8 p2 200 steps")
     spec = workloads.COUETTE_8x8_P2_D2Q16

@@ -186,6 +186,52 @@ def test_residual_and_moments_parity(oracle_mod):
     assert g2.residual() < 1e-12
 
 
+def _moment_field(g, seed):
+    """Seeded smooth density and velocity at every node (shape K, Np)."""
+    x, y = g.node_coords()
+    r = np.random.default_rng(seed).uniform(0.5, 1.5, size=4)
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * r[0] * x) * np.cos(2 * np.pi * r[1] * y)
+    ux = 0.1 * np.cos(2 * np.pi * r[2] * y)
+    uy = -0.08 * np.sin(2 * np.pi * r[3] * x)
+    return rho, ux, uy
+
+
+@pytest.mark.parametrize("name,spec", [
+    ("cavity_6x5_p2_nc8", workloads.cavity(n=6, ny=5, p=2, m=8, lid=0.1)),
+    ("couette_7x3_p3_gh6", workloads.couette(nx=7, ny=3, p=3, velset=("gh", 6))),
+], ids=lambda v: v if isinstance(v, str) else "")
+def test_init_moments_matches_oracle_equilibrium(oracle_mod, name, spec):
+    _say(f"[gpu] init_moments {name}")
+    g, o = _pair(oracle_mod, spec)
+    rho, ux, uy = _moment_field(g, 11)
+    g.init_moments(rho, ux, uy)
+    f = g.get_state()
+    want = np.empty_like(f)
+    for k in range(o.K):
+        for n in range(o.Np):
+            want[:, k, n] = o.equilibrium(rho[k, n], ux[k, n], uy[k, n])
+    assert _rel(f, want) < 1e-14
+    # the steps from that state follow the oracle's
+    o.set_state(want)
+    dt = g.stable_dt(0.2)
+    g.step(20, dt)
+    o.rk4(20, dt)
+    er, eu = _moment_errors(g, o)
+    _say(f"    rho {er:.2e}  u {eu:.2e}")
+    assert er < TOL and eu < TOL
+
+
+def test_init_moments_uniform_equals_init_equilibrium():
+    _say("[gpu] init_moments uniform")
+    spec = workloads.cavity(n=5, p=3, m=8, lid=0.1)
+    a = binding.Solver.from_spec(spec)
+    b = binding.Solver.from_spec(spec)
+    shape = (a.K, a.Np)
+    a.init_moments(np.full(shape, 1.3), np.full(shape, 0.02), np.full(shape, -0.05))
+    b.init_equilibrium(1.3, 0.02, -0.05)
+    assert np.array_equal(a.get_state(), b.get_state())
+
+
 def test_residual_async_and_nonfinite():
     _say("[gpu] residual async / nonfinite")
     import torch
