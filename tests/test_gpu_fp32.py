@@ -2,7 +2,8 @@
 the deviation from w_q rho_ref; moments, wall densities and residual in FP64)
 against the FP64 CPU oracle on the same seeded inputs, and against the GPU
 FP64 path at the full precision-workload size; and of its variant with the
-volume term's contractions on bf16 matrix cores.
+volume term's contractions on bf16 matrix cores.  The full-size precision
+workload also checks the FP64 path in its velocity-tiled form (bar 1e-12).
 
 Bars: FP32 storage, 1e-5 relative in max-norm on rho and u (normwise over
 nodes and components for u, as in the FP64 tests) after the same RK4 steps
@@ -21,6 +22,7 @@ from paper_2012_13487_amd import binding
 
 pytestmark = pytest.mark.gpu
 
+TOL64 = 1e-12  # the FP64 path's bar
 TOL32 = 1e-5
 TOL_BF = 2e-3
 TOL_BF_RHS = 4e-3
@@ -235,17 +237,19 @@ def test_bf16_steps(oracle_mod, spec):
     assert er < TOL_BF and eu < TOL_BF, (er, eu)
 
 
-def test_fp32_and_bf16_full_size_precision_workload(oracle_mod):
+def test_full_size_precision_workload_all_precisions(oracle_mod):
     """128 x 128 quads, p = 4, NC 24 x 24, Kn = 8 (235.9 M DOF) in the launch
-    configuration the benchmark times, for both FP32 precisions: the
-    right-hand side of a perturbed state against the oracle, and rho, u after
-    10 RK4 steps from rest against the oracle."""
-    _say("[gpu] fp32 / bf16 full-size cavity 128x128 p4 nc24 kn8")
+    configuration the benchmark times, for the FP64 path (velocity tiles: one
+    element's 576 velocities exceed the fused block's LDS in FP64) and both
+    FP32 precisions: the right-hand side of a perturbed state against the
+    oracle, and rho, u after 10 RK4 steps from rest against the oracle."""
+    _say("[gpu] fp64 / fp32 / bf16 full-size cavity 128x128 p4 nc24 kn8")
     spec = workloads.CAVITY_128x128_P4_NC24_KN8
     o = oracle_mod.Oracle.from_spec(spec)
     f = workloads.perturbed_state(41, o.w, o.K, o.Np, amp=0.05)
     ko = o.rhs(f)
-    for prec, tol in ((binding.FP32, TOL32), (binding.FP32_BF16MMA, TOL_BF_RHS)):
+    for prec, tol in ((binding.FP64, TOL64), (binding.FP32, TOL32),
+                      (binding.FP32_BF16MMA, TOL_BF_RHS)):
         g = binding.Solver.from_spec(spec, precision=prec, stream="torch", torch_memory=True)
         e = _rel(g.rhs(f), ko)
         _say(f"  rhs prec {prec}: {e:.2e}")
@@ -257,8 +261,10 @@ def test_fp32_and_bf16_full_size_precision_workload(oracle_mod):
     _say("  10 oracle steps")
     o.rk4(10, dt)
     mo = o.moments()
-    for prec, tol in ((binding.FP32, TOL32), (binding.FP32_BF16MMA, TOL_BF)):
+    for prec, tol in ((binding.FP64, TOL64), (binding.FP32, TOL32), (binding.FP32_BF16MMA, TOL_BF)):
         g = binding.Solver.from_spec(spec, precision=prec, stream="torch", torch_memory=True)
+        if prec == binding.FP64:
+            assert not g.tiling()["fused"]
         g.init_equilibrium()
         g.step(10, dt)
         er, eu = _moment_errors(g.moments(), mo)
