@@ -57,7 +57,10 @@ RHS_CASES = [
     ("cavity_5x3_p4_nc5_scalar", workloads.cavity(n=5, ny=3, p=4, m=5, lid=0.2)),  # Q Np odd
     ("periodic_7x3_p1_gh3", workloads.periodic_box(nx=7, ny=3, p=1, velset=("gh", 3), kn=0.3)),
     ("cavity_9x7_p3_nc9", workloads.cavity(n=9, ny=7, p=3, m=9, lid=0.15)),
+    ("couette_3x1_p5_gh4", workloads.couette(nx=3, ny=1, p=5)),
     ("cavity_3x2_p6_nc4", workloads.cavity(n=3, ny=2, p=6, m=4)),
+    ("cavity_2x3_p7_nc5", workloads.cavity(n=2, ny=3, p=7, m=5, lid=0.2)),
+    ("cavity_2x2_p8_nc5_scalar", workloads.cavity(n=2, p=8, m=5)),  # Q Np odd
     ("collisionless_4x4_p3", workloads.periodic_box(nx=4, ny=4, p=3, tau=float("inf"))),
     # strip-ordered blocks: one element per block (20 columns, strips of 16)
     ("cavity_20x3_p2_nc16_strips", workloads.cavity(n=20, ny=3, p=2, m=16, lid=0.1)),
@@ -123,6 +126,22 @@ def test_fp32_init_moments(oracle_mod):
     assert _rel(g.get_state(), want) < 2 ** -23
     o.set_state(want)
     er, eu = _moment_errors(g.moments(), o.moments())
+    assert er < TOL32 and eu < TOL32
+
+
+@pytest.mark.parametrize("p", [5, 7, 8])
+def test_fp32_high_order_steps(oracle_mod, p):
+    _say(f"[gpu] fp32 steps p={p}")
+    spec = workloads.cavity(n=3, ny=2, p=p, m=6, lid=0.1)
+    g, o = _pair(oracle_mod, spec)
+    f = workloads.perturbed_state(5, o.w, o.K, o.Np, amp=0.1)
+    g.set_state(f)
+    o.set_state(f)
+    dt = o.stable_dt(0.2)
+    g.step(20, dt)
+    o.rk4(20, dt)
+    er, eu = _moment_errors(g.moments(), o.moments())
+    _say(f"    rho {er:.2e}  u {eu:.2e}")
     assert er < TOL32 and eu < TOL32
 
 
