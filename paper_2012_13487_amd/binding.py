@@ -359,6 +359,14 @@ class Solver:
         self._call("dgbgk_get_state", _p(f), f.size)
         return f.reshape(self.shape)
 
+    def set_stream(self, stream):
+        """Later calls enqueue on stream (a HIP stream handle, or "torch" for
+        torch's current stream)."""
+        if stream == "torch":
+            import torch  # plumbing only: the stream
+            stream = torch.cuda.current_stream().cuda_stream
+        self._call("dgbgk_set_stream", C.c_void_p(stream or 0))
+
     def state_device_ptr(self):
         ptr = C.c_void_p()
         self._call("dgbgk_state_device_ptr", C.byref(ptr))

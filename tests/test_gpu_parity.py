@@ -232,6 +232,38 @@ def test_init_moments_uniform_equals_init_equilibrium():
     assert np.array_equal(a.get_state(), b.get_state())
 
 
+def test_stream_switch_and_device_state_view():
+    """Work enqueued on a caller's stream after dgbgk_set_stream gives the
+    same state as on the null stream; dgbgk_state_device_ptr is the
+    element-major device copy of the state."""
+    import torch
+    _say("[gpu] set_stream / state_device_ptr")
+    spec = workloads.cavity(n=5, ny=4, p=3, m=8, lid=0.1)
+    a = binding.Solver.from_spec(spec)
+    b = binding.Solver.from_spec(spec)
+    dt = a.stable_dt(0.2)
+    a.init_equilibrium()
+    a.step(15, dt)
+    side = torch.cuda.Stream()
+    b.set_stream(side.cuda_stream)
+    b.init_equilibrium()
+    b.step(15, dt)
+    b.synchronize()
+    fa, fb = a.get_state(), b.get_state()
+    b.set_stream(None)  # the side stream may go away before b does
+    assert np.array_equal(fa, fb)
+
+    # copy the device state out with the HIP runtime the process has loaded
+    import ctypes
+    path = next(ln.split()[-1] for ln in open("/proc/self/maps") if "libamdhip64" in ln)
+    hip = ctypes.CDLL(path)
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip.hipMemcpy.restype = ctypes.c_int
+    dev = np.empty((b.K, b.Q, b.Np))
+    assert hip.hipMemcpy(dev.ctypes.data, b.state_device_ptr(), dev.nbytes, 2) == 0  # to host
+    assert np.array_equal(dev.transpose(1, 0, 2), fb)
+
+
 def test_residual_async_and_nonfinite():
     _say("[gpu] residual async / nonfinite")
     import torch
