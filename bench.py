@@ -256,6 +256,17 @@ def implicit_path(steps=2, mult=10.0, race_target=1e-6):
            "simulated_time_per_s": mult * dt / imp_s,
            "explicit_rk4_simulated_time_per_s": dt / exp_s}
     out["implicit_over_explicit"] = out["simulated_time_per_s"] / out["explicit_rk4_simulated_time_per_s"]
+    # the Krylov basis in FP32 against FP64 at the loosest tolerance it allows
+    basis = {"krylov_rtol": 1e-5}
+    for name, fp32 in (("fp64_basis", False), ("fp32_basis", True)):
+        g.init_equilibrium()
+        g.implicit_step(1, mult * dt, "backward_euler", krylov_rtol=1e-5, krylov_fp32=fp32)
+        t0 = time.perf_counter()
+        rep = g.implicit_step(steps, mult * dt, "backward_euler", krylov_rtol=1e-5, krylov_fp32=fp32)
+        basis[name] = {"ms_per_step": (time.perf_counter() - t0) / steps * 1e3,
+                       "krylov_per_step": rep["krylov_iterations"] / steps}
+    basis["fp32_over_fp64_speed"] = basis["fp64_basis"]["ms_per_step"] / basis["fp32_basis"]["ms_per_step"]
+    out["krylov_basis"] = basis
     del g
 
     small = workloads.cavity(n=8, p=2, m=8, lid=0.1, kn=1.0)

@@ -269,7 +269,8 @@ int dgbgk_autotune(dgbgk_solver *s, int32_t launches, double *best_us);
  * side kernels as the explicit path; f_{n+1} = y_s.  Vector reductions are
  * deterministic, so a call is bitwise reproducible.  FP64 precision only
  * (DGBGK_ENOTSUP otherwise).  The library allocates a device workspace of
- * (m + stages + 6) state-sized vectors at the first call (kept until destroy,
+ * (m + stages + 6) state-sized vectors (FP32 basis: stages + 6 plus m + 1
+ * vectors of half size) at the first call (kept until destroy,
  * regrown if a later call needs more).  Norms are root-mean-square over all
  * K Np Q values.  A stage's Newton iteration stops when its nonlinear residual
  * |y - b - dt gamma L(y)| falls to newton_rtol times its value at the initial
@@ -279,7 +280,7 @@ int dgbgk_autotune(dgbgk_solver *s, int32_t launches, double *best_us);
  * max_krylov iterations, or on breakdown.  The difference step is 1e-6
  * (1 + |y|_2) for a unit vector.  opt may be NULL:
  * max_newton 20, newton_rtol 1e-10, newton_atol 1e-14, restart 30,
- * max_krylov 300, krylov_rtol 1e-6. */
+ * max_krylov 300, krylov_rtol 1e-6, krylov_fp32 0. */
 typedef enum { DGBGK_BACKWARD_EULER = 0, DGBGK_SDIRK2 = 1, DGBGK_SDIRK4 = 2 } dgbgk_implicit_scheme;
 
 typedef struct {
@@ -291,6 +292,12 @@ typedef struct {
                            a cycle that reduces the residual by < 10%      */
   int32_t max_krylov;   /* GMRES iterations per Newton step (>= 1)        */
   double krylov_rtol;   /* in (0, 1)                                      */
+  int32_t krylov_fp32;  /* 1: the Krylov basis is stored in FP32 (half its
+                           traffic; the residual, the Krylov vector being
+                           orthogonalised, the projections and the
+                           solution stay FP64).  The basis is then
+                           orthonormal to about 1e-7, so krylov_rtol must
+                           be >= 1e-5.  0: FP64 basis                      */
 } dgbgk_implicit_options;
 
 typedef struct {

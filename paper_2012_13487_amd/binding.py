@@ -64,7 +64,7 @@ class ImplicitOptions(C.Structure):
     """Mirror of dgbgk_implicit_options."""
     _fields_ = [("max_newton", C.c_int32), ("newton_rtol", C.c_double),
                 ("newton_atol", C.c_double), ("restart", C.c_int32), ("max_krylov", C.c_int32),
-                ("krylov_rtol", C.c_double)]
+                ("krylov_rtol", C.c_double), ("krylov_fp32", C.c_int32)]
 
 
 class ImplicitReport(C.Structure):
@@ -376,11 +376,13 @@ class Solver:
         self._call("dgbgk_step", int(nsteps), float(dt))
 
     def implicit_step(self, nsteps, dt, scheme="backward_euler", max_newton=20, newton_rtol=1e-10,
-                      newton_atol=1e-14, restart=30, max_krylov=300, krylov_rtol=1e-6):
-        """nsteps SDIRK steps (Newton with matrix-free GMRES); returns the report as a dict."""
+                      newton_atol=1e-14, restart=30, max_krylov=300, krylov_rtol=1e-6,
+                      krylov_fp32=False):
+        """nsteps SDIRK steps (Newton with matrix-free GMRES); returns the report as a dict.
+        krylov_fp32: store the Krylov basis in FP32 (needs krylov_rtol >= 1e-5)."""
         sc = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
         o = ImplicitOptions(int(max_newton), float(newton_rtol), float(newton_atol), int(restart),
-                            int(max_krylov), float(krylov_rtol))
+                            int(max_krylov), float(krylov_rtol), int(krylov_fp32))
         r = ImplicitReport()
         self._call("dgbgk_implicit_step", sc, int(nsteps), float(dt), C.byref(o), C.byref(r))
         return {name: getattr(r, name) for name, _ in ImplicitReport._fields_}

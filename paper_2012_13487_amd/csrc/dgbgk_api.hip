@@ -1189,18 +1189,21 @@ struct ImplicitWs {
   size_t n = 0, stride = 0;
   double *K = nullptr;  // stages x stride: L(y_i)
   double *y = nullptr, *b = nullptr, *F = nullptr, *T = nullptr, *X = nullptr;
-  double *V = nullptr;  // (m + 1) x stride
+  double *V = nullptr;  // (m + 1) x stride (FP64 basis)
+  double *W = nullptr;  // the vector being orthogonalised (FP32 basis)
+  float *V32 = nullptr;  // (m + 1) x stride floats (FP32 basis)
   double *dots = nullptr;   // multi-dot scratch
   double *small = nullptr;  // h1[m+1], h2[m+1], |w|^2, spare
   double *coef = nullptr;   // kMaxBasis coefficients uploaded from the host
 };
 
-size_t implicit_ws_bytes(size_t n, int stages, int m, size_t *stride) {
+size_t implicit_ws_bytes(size_t n, int stages, int m, bool v32, size_t *stride) {
   const size_t st = (n + 31) / 32 * 32;
   if (stride) *stride = st;
-  const size_t vecs = (size_t)stages + 5 + (size_t)(m + 1);
+  const size_t vecs = (size_t)stages + 5 + (v32 ? 1 : (size_t)(m + 1));
+  const size_t basis32 = v32 ? (size_t)(m + 1) * st / 2 : 0;  // st is even
   const size_t small = multi_dot_scratch(n, m + 1) + 2 * (size_t)(m + 1) + 8 + kMaxBasis;
-  return (vecs * st + small) * sizeof(double);
+  return (vecs * st + basis32 + small) * sizeof(double);
 }
 
 struct Implicit {
@@ -1213,6 +1216,7 @@ struct Implicit {
   std::vector<double> host_small, host_coef;
 
   double *Vk(int k) const { return w.V + (size_t)k * w.stride; }
+  float *Vk32(int k) const { return w.V32 + (size_t)k * w.stride; }
 
   int check(hipError_t e, const char *what) { return e == hipSuccess ? DGBGK_OK : hip_fail(s, e, what); }
 
@@ -1366,6 +1370,132 @@ struct Implicit {
     return DGBGK_OK;
   }
 
+  // apply() for a vector v of the FP32 basis; out (FP64) != T.
+  int apply32(const float *v, double vnorm, const double *Ly, double *out) {
+    const double e = eps / vnorm;
+    int rc = check(launch_lincomb_mixed(w.n, 1.0, w.y, e, v, 0.0, nullptr, w.T, s->stream), "lincomb");
+    if (!rc) rc = rhs(w.T, out);
+    if (!rc)
+      rc = check(launch_lincomb_mixed(w.n, -h / e, out, 1.0, v, h / e, Ly, out, s->stream), "lincomb");
+    return rc;
+  }
+
+  // GMRES as above with the basis stored in FP32: each new Krylov vector is
+  // formed and orthogonalised in FP64 (w.W) against the FP32 basis, and
+  // stored in FP32 once normalised; restarts form the true residual in FP64.
+  int gmres32(const double *Ly, double fnorm2, double tol2, int max_it, int &iters) {
+    const size_t n = w.n;
+    std::vector<double> R((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), yv(m);
+    int rc = check(launch_lincomb(n, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, w.X, s->stream), "zero");
+    if (rc) return rc;
+    double beta = fnorm2;
+    int mc = std::min(kShortCycle, m);
+    rc = check(launch_multi_axpy32(n, 0, w.V32, w.stride, w.coef, 0.0, w.F, -1.0 / beta, w.W, Vk32(0),
+                                   s->stream),
+               "basis vector");
+    if (rc) return rc;
+    bool done = false;
+    while (!done) {
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int jn = 0;
+      const double beta_cycle = beta;
+      for (int j = 0; j < mc; ++j) {
+        if ((rc = apply32(Vk32(j), 1.0, Ly, w.W))) return rc;
+        // projections on V_0..V_j and |w|^2 in one pass
+        double *h1 = w.small, *h2 = w.small + (m + 1);
+        hipError_t e = launch_multi_dot32(n, j + 1, w.V32, w.stride, w.W, w.dots, h1, s->stream);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(host_small.data(), h1, (size_t)(j + 2) * sizeof(double),
+                             hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return hip_fail(s, e, "Arnoldi projections");
+        double *col = &R[(size_t)j * (m + 1)];
+        double hh = 0.0;
+        for (int i = 0; i <= j; ++i) {
+          col[i] = host_small[i];
+          hh += col[i] * col[i];
+        }
+        const double ww = host_small[j + 1];
+        if (!std::isfinite(ww) || !std::isfinite(hh))
+          return fail(s, DGBGK_ENONFINITE, "Krylov vector is not finite");
+        double hn;
+        if (ww - hh > 0.5 * ww) {
+          hn = std::sqrt(ww - hh);
+          e = launch_multi_axpy32(n, j + 1, w.V32, w.stride, h1, -1.0, w.W, 1.0 / hn, w.W, Vk32(j + 1),
+                                  s->stream);
+        } else {
+          e = launch_multi_axpy32(n, j + 1, w.V32, w.stride, h1, -1.0, w.W, 1.0, w.W, nullptr, s->stream);
+          if (e == hipSuccess) e = launch_multi_dot32(n, j + 1, w.V32, w.stride, w.W, w.dots, h2, s->stream);
+          if (e == hipSuccess)
+            e = hipMemcpyAsync(host_small.data(), h2, (size_t)(j + 2) * sizeof(double),
+                               hipMemcpyDeviceToHost, s->stream);
+          if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+          if (e != hipSuccess) return hip_fail(s, e, "Arnoldi reorthogonalisation");
+          double hh2 = 0.0;
+          for (int i = 0; i <= j; ++i) {
+            col[i] += host_small[i];
+            hh2 += host_small[i] * host_small[i];
+          }
+          hn = std::sqrt(std::max(host_small[j + 1] - hh2, 0.0));
+          e = launch_multi_axpy32(n, j + 1, w.V32, w.stride, h2, -1.0, w.W, hn > 0.0 ? 1.0 / hn : 1.0, w.W,
+                                  Vk32(j + 1), s->stream);
+        }
+        if (e != hipSuccess) return hip_fail(s, e, "Arnoldi update");
+        for (int i = 0; i < j; ++i) {
+          const double a = col[i], b = col[i + 1];
+          col[i] = cs[i] * a + sn[i] * b;
+          col[i + 1] = -sn[i] * a + cs[i] * b;
+        }
+        const double den = std::hypot(col[j], hn);
+        cs[j] = den > 0 ? col[j] / den : 1.0;
+        sn[j] = den > 0 ? hn / den : 0.0;
+        col[j] = den;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++iters;
+        jn = j + 1;
+        const bool breakdown = !(hn > 0.0);
+        if (std::fabs(g[j + 1]) <= tol2 || breakdown || iters >= max_it) {
+          done = true;
+          break;
+        }
+      }
+      for (int i = jn - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int k = i + 1; k < jn; ++k) t -= R[(size_t)k * (m + 1) + i] * yv[k];
+        const double d = R[(size_t)i * (m + 1) + i];
+        yv[i] = d != 0.0 ? t / d : 0.0;
+      }
+      for (int i = 0; i < jn; ++i) host_coef[i] = yv[i];
+      hipError_t e = hipMemcpyAsync(w.coef, host_coef.data(), jn * sizeof(double),
+                                    hipMemcpyHostToDevice, s->stream);
+      if (e == hipSuccess)
+        e = launch_multi_axpy32(n, jn, w.V32, w.stride, w.coef, 1.0, w.X, 1.0, w.X, nullptr, s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // host_coef is reused
+      if (e != hipSuccess) return hip_fail(s, e, "GMRES update");
+      if (done) break;
+      double xn2 = 0.0;
+      if ((rc = dot(w.X, w.X, xn2))) return rc;
+      const double xn = std::sqrt(xn2);
+      if (!(xn > 0.0)) break;
+      if ((rc = apply(w.X, xn, Ly, w.W))) return rc;
+      if ((rc = check(launch_lincomb(n, -1.0, w.W, -1.0, w.F, 0.0, nullptr, w.W, s->stream), "lincomb")))
+        return rc;
+      double r2 = 0.0;
+      if ((rc = dot(w.W, w.W, r2))) return rc;
+      beta = std::sqrt(r2);
+      if (!std::isfinite(beta)) return fail(s, DGBGK_ENONFINITE, "GMRES residual is not finite");
+      if (beta <= tol2) break;
+      if (beta > 0.9 * beta_cycle) mc = std::min(2 * mc, m);
+      if ((rc = check(launch_multi_axpy32(n, 0, w.V32, w.stride, w.coef, 0.0, w.W, 1.0 / beta, w.W,
+                                          Vk32(0), s->stream),
+                      "basis vector")))
+        return rc;
+    }
+    return DGBGK_OK;
+  }
+
   // F = y - b - h Ly and its 2-norm.
   int newton_residual(const double *Ly, double &fn2) {
     int rc = check(launch_lincomb(w.n, 1.0, w.y, -1.0, w.b, -h, Ly, w.F, s->stream), "lincomb");
@@ -1388,12 +1518,15 @@ int dgbgk_implicit_step(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double 
   Sdirk tab;
   if (!sdirk_tableau(scheme, tab)) return fail(s, DGBGK_EINVAL, "unknown implicit scheme %d", scheme);
   if (nsteps < 0 || !(dt > 0) || !is_finite_d(dt)) return fail(s, DGBGK_EINVAL, "need nsteps >= 0, dt > 0");
-  dgbgk_implicit_options o{20, 1e-10, 1e-14, 30, 300, 1e-6};
+  dgbgk_implicit_options o{20, 1e-10, 1e-14, 30, 300, 1e-6, 0};
   if (opt) o = *opt;
   if (o.max_newton < 1 || o.max_newton > 1000 || o.restart < 1 || o.restart > 64 || o.max_krylov < 1 ||
       !(o.newton_rtol >= 0) || !(o.newton_atol >= 0) || !is_finite_d(o.newton_rtol) ||
-      !is_finite_d(o.newton_atol) || !(o.krylov_rtol > 0 && o.krylov_rtol < 1))
+      !is_finite_d(o.newton_atol) || !(o.krylov_rtol > 0 && o.krylov_rtol < 1) ||
+      (o.krylov_fp32 != 0 && o.krylov_fp32 != 1))
     return fail(s, DGBGK_EINVAL, "implicit options out of range");
+  if (o.krylov_fp32 && o.krylov_rtol < 1e-5)
+    return fail(s, DGBGK_EINVAL, "an FP32 Krylov basis needs krylov_rtol >= 1e-5");
   if (s->prec != DGBGK_FP64) return fail(s, DGBGK_ENOTSUP, "implicit steps need FP64 precision");
   if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
   int rc = ensure_device(s);
@@ -1403,7 +1536,8 @@ int dgbgk_implicit_step(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double 
   Implicit im{s, ImplicitWs{}, o.restart};
   const size_t n = (size_t)s->K * s->Np * s->Q;
   size_t stride = 0;
-  const size_t bytes = implicit_ws_bytes(n, tab.stages, im.m, &stride);
+  const bool v32 = o.krylov_fp32 != 0;
+  const size_t bytes = implicit_ws_bytes(n, tab.stages, im.m, v32, &stride);
   if (bytes > s->imp_bytes) {
     if (s->imp_ws) {
       (void)hipStreamSynchronize(s->stream);
@@ -1427,7 +1561,12 @@ int dgbgk_implicit_step(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double 
   w.F = q;  q += stride;
   w.T = q;  q += stride;
   w.X = q;  q += stride;
-  w.V = q;  q += (size_t)(im.m + 1) * stride;
+  if (v32) {
+    w.W = q;  q += stride;
+    w.V32 = (float *)q;  q += (size_t)(im.m + 1) * stride / 2;
+  } else {
+    w.V = q;  q += (size_t)(im.m + 1) * stride;
+  }
   w.dots = q;  q += multi_dot_scratch(n, im.m + 1);
   w.small = q;  q += 2 * (size_t)(im.m + 1) + 8;
   w.coef = q;
@@ -1466,7 +1605,9 @@ int dgbgk_implicit_step(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double 
         int kit = 0;
         // inexact Newton: no linear solve tighter than the Newton target needs
         const double ktol = std::max(o.krylov_rtol * fn2, 0.1 * target);
-        if ((rc = im.gmres(Ly, fn2, ktol, o.max_krylov, kit))) return rc;
+        if ((rc = v32 ? im.gmres32(Ly, fn2, ktol, o.max_krylov, kit)
+                      : im.gmres(Ly, fn2, ktol, o.max_krylov, kit)))
+          return rc;
         krylov_total += kit;
         ++newton_total;
         if ((rc = im.check(launch_lincomb(n, 1.0, w.y, 1.0, w.X, 0.0, nullptr, w.y, s->stream), "lincomb")))

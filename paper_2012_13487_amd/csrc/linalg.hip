@@ -1,4 +1,5 @@
-// FP64 vector kernels of the implicit time step: a fused linear combination,
+// Vector kernels of the implicit time step (FP64 vectors; the Krylov basis in
+// FP64 or FP32): a fused linear combination,
 // a deterministic multi-vector dot product (Gram-Schmidt projections of the
 // Krylov basis) and the matching multi-vector update with scaling.  All are HBM-bound
 // streams; the dot kernel reads w once per four basis vectors.
@@ -25,6 +26,19 @@ __global__ __launch_bounds__(kBlock) void lincomb_kernel(size_t n, double a, con
   }
 }
 
+// out = a x + b y + c z with y in FP32 (a Krylov vector of the FP32 basis).
+__global__ __launch_bounds__(kBlock) void lincomb_mixed_kernel(size_t n, double a, const double *x,
+                                                               double b, const float *y, double c,
+                                                               const double *z, double *out) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double v = x ? a * x[i] : 0.0;
+    if (y) v += b * (double)y[i];
+    if (z) v += c * z[i];
+    out[i] = v;
+  }
+}
+
 // Sum of v over the work-group, valid in thread 0; red is reusable on return.
 __device__ inline double block_sum(double v, double *red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -40,7 +54,9 @@ __device__ inline double block_sum(double v, double *red) {
 
 // Work-group (g, j) sums V_k . w for k = kVecs j ... kVecs j + kVecs - 1 over
 // the chunks g, g + G, g + 2G, ... of kBlock * kItems elements.
-__global__ __launch_bounds__(kBlock) void multi_dot_partial_kernel(size_t n, int nv, const double *V,
+// T: element type of the basis.  SELF: vector nv is w itself (w . w).
+template <typename T, bool SELF>
+__global__ __launch_bounds__(kBlock) void multi_dot_partial_kernel(size_t n, int nv, const T *V,
                                                                    size_t vstride, const double *w,
                                                                    double *partial) {
   __shared__ double red[kBlock / 64];
@@ -57,15 +73,17 @@ __global__ __launch_bounds__(kBlock) void multi_dot_partial_kernel(size_t n, int
       if (i < n) {
         const double wi = w[i];
 #pragma unroll
-        for (int t = 0; t < kVecs; ++t)
-          if (k0 + t < nv) acc[t] += V[(size_t)(k0 + t) * vstride + i] * wi;
+        for (int t = 0; t < kVecs; ++t) {
+          if (k0 + t < nv) acc[t] += (double)V[(size_t)(k0 + t) * vstride + i] * wi;
+          else if (SELF && k0 + t == nv) acc[t] += wi * wi;
+        }
       }
     }
   }
 #pragma unroll
   for (int t = 0; t < kVecs; ++t) {
     const double s = block_sum(acc[t], red);
-    if (threadIdx.x == 0 && k0 + t < nv) partial[(size_t)(k0 + t) * G + blockIdx.x] = s;
+    if (threadIdx.x == 0 && k0 + t < nv + (SELF ? 1 : 0)) partial[(size_t)(k0 + t) * G + blockIdx.x] = s;
   }
 }
 
@@ -80,15 +98,19 @@ __global__ __launch_bounds__(kBlock) void multi_dot_final_kernel(int G, const do
   if (threadIdx.x == 0) result[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void multi_axpy_kernel(size_t n, int nv, const double *V,
+// out32 (optional): an FP32 copy of out.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void multi_axpy_kernel(size_t n, int nv, const T *V,
                                                             size_t vstride, const double *coef,
                                                             double alpha, const double *w,
-                                                            double scale, double *out) {
+                                                            double scale, double *out, float *out32) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     double s = 0.0;
-    for (int k = 0; k < nv; ++k) s += coef[k] * V[(size_t)k * vstride + i];
-    out[i] = scale * (w[i] + alpha * s);
+    for (int k = 0; k < nv; ++k) s += coef[k] * (double)V[(size_t)k * vstride + i];
+    const double r = scale * (w[i] + alpha * s);
+    out[i] = r;
+    if (out32) out32[i] = (float)r;
   }
 }
 
@@ -122,8 +144,8 @@ hipError_t launch_multi_dot(size_t n, int nv, const double *V, size_t vstride, c
   if (nv < 1 || nv > kMaxBasis) return hipErrorInvalidValue;
   const int G = dot_groups(n);
   const unsigned gy = (unsigned)((nv + kVecs - 1) / kVecs);
-  hipLaunchKernelGGL(multi_dot_partial_kernel, dim3((unsigned)G, gy), dim3(kBlock), 0, st, n, nv, V,
-                     vstride, w, scratch);
+  hipLaunchKernelGGL((multi_dot_partial_kernel<double, false>), dim3((unsigned)G, gy), dim3(kBlock), 0,
+                     st, n, nv, V, vstride, w, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(multi_dot_final_kernel, dim3((unsigned)nv), dim3(kBlock), 0, st, G, scratch,
@@ -136,8 +158,41 @@ hipError_t launch_multi_axpy(size_t n, int nv, const double *V, size_t vstride, 
                              hipStream_t st) {
   if (nv < 0 || nv > kMaxBasis) return hipErrorInvalidValue;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(multi_axpy_kernel, dim3(stream_blocks(n)), dim3(kBlock), 0, st, n, nv, V,
-                     vstride, coef, alpha, w, scale, out);
+  hipLaunchKernelGGL(multi_axpy_kernel<double>, dim3(stream_blocks(n)), dim3(kBlock), 0, st, n, nv, V,
+                     vstride, coef, alpha, w, scale, out, (float *)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb_mixed(size_t n, double a, const double *x, double b, const float *y,
+                                double c, const double *z, double *out, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(lincomb_mixed_kernel, dim3(stream_blocks(n)), dim3(kBlock), 0, st, n, a, x, b, y,
+                     c, z, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_dot32(size_t n, int nv, const float *V, size_t vstride, const double *w,
+                              double *scratch, double *result, hipStream_t st) {
+  if (nv < 0 || nv + 1 > kMaxBasis) return hipErrorInvalidValue;
+  const int G = dot_groups(n);
+  const int nt = nv + 1;
+  const unsigned gy = (unsigned)((nt + kVecs - 1) / kVecs);
+  hipLaunchKernelGGL((multi_dot_partial_kernel<float, true>), dim3((unsigned)G, gy), dim3(kBlock), 0,
+                     st, n, nv, V, vstride, w, scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(multi_dot_final_kernel, dim3((unsigned)nt), dim3(kBlock), 0, st, G, scratch,
+                     result);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy32(size_t n, int nv, const float *V, size_t vstride, const double *coef,
+                               double alpha, const double *w, double scale, double *out, float *out32,
+                               hipStream_t st) {
+  if (nv < 0 || nv > kMaxBasis) return hipErrorInvalidValue;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(multi_axpy_kernel<float>, dim3(stream_blocks(n)), dim3(kBlock), 0, st, n, nv, V,
+                     vstride, coef, alpha, w, scale, out, out32);
   return hipGetLastError();
 }
 

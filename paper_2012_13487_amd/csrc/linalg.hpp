@@ -1,4 +1,4 @@
-// FP64 vector kernels of the implicit (Newton-Krylov) time step.  Every
+// Vector kernels of the implicit (Newton-Krylov) time step.  Every
 // reduction has a fixed assignment of elements to work-groups and a fixed
 // summation order for a given length, so results are bitwise reproducible.
 #pragma once
@@ -30,5 +30,21 @@ hipError_t launch_multi_dot(size_t n, int nv, const double *V, size_t stride, co
 hipError_t launch_multi_axpy(size_t n, int nv, const double *V, size_t stride, const double *coef,
                              double alpha, const double *w, double scale, double *out,
                              hipStream_t stream);
+
+// The same operations with the Krylov basis V stored in FP32 (w, coef and
+// out stay FP64).  lincomb_mixed: out = a x + b y + c z with y in FP32.
+hipError_t launch_lincomb_mixed(size_t n, double a, const double *x, double b, const float *y,
+                                double c, const double *z, double *out, hipStream_t stream);
+
+// result[k] = V_k . w for k < nv and result[nv] = w . w (nv + 1 <= kMaxBasis);
+// scratch holds multi_dot_scratch(n, nv + 1) doubles.
+hipError_t launch_multi_dot32(size_t n, int nv, const float *V, size_t stride, const double *w,
+                              double *scratch, double *result, hipStream_t stream);
+
+// out = scale (w + alpha sum_{k < nv} coef[k] V_k); out32, when not null,
+// receives out rounded to FP32.  out may alias w.
+hipError_t launch_multi_axpy32(size_t n, int nv, const float *V, size_t stride, const double *coef,
+                               double alpha, const double *w, double scale, double *out,
+                               float *out32, hipStream_t stream);
 
 }  // namespace dgbgk

@@ -197,6 +197,10 @@ def test_device_calls_fail_loudly_without_gpu():
     with pytest.raises(binding.DgbgkError) as ei:
         s.implicit_step(1, 1e-3, scheme=9)
     assert ei.value.code == binding.EINVAL
+    for bad in (dict(krylov_fp32=True, krylov_rtol=1e-6), dict(krylov_fp32=2)):
+        with pytest.raises(binding.DgbgkError) as ei:
+            s.implicit_step(1, 1e-3, **bad)
+        assert ei.value.code == binding.EINVAL
 
 
 def test_server_validation_and_cpu_failure_path():

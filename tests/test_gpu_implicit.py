@@ -89,6 +89,50 @@ def test_uniform_relaxation_closed_form(oracle_mod):
         assert err < 1e-12 * np.max(np.abs(f0 - feq)) * (1.0 + ratio), (ratio, err)
 
 
+# FP32 Krylov basis: the linear solves stop at 1e-5 (the basis is orthonormal
+# to about 1e-7), so Newton takes more, looser steps to the same tolerance.
+TIGHT32 = dict(newton_rtol=1e-13, newton_atol=1e-17, krylov_rtol=1e-5, max_krylov=400,
+               max_newton=60, krylov_fp32=True)
+
+
+@pytest.mark.parametrize("scheme,nsteps,cfl_mult", [("backward_euler", 2, 10.0), ("sdirk4", 1, 5.0)])
+@pytest.mark.parametrize("name,spec,tiling", CASES, ids=[c[0] for c in CASES])
+def test_implicit_step_parity_fp32_basis(oracle_mod, name, spec, tiling, scheme, nsteps, cfl_mult):
+    _say(f"[gpu] implicit parity, FP32 Krylov basis, {name} {scheme} x{nsteps}")
+    g = binding.Solver.from_spec(spec)
+    if tiling is not None:
+        g.set_tiling(*tiling)
+    o = oracle_mod.Oracle.from_spec(spec)
+    f0 = workloads.perturbed_state(21, o.w, o.K, o.Np, amp=0.15)
+    dt = cfl_mult * o.stable_dt(0.2)
+    g.set_state(f0)
+    rep = g.implicit_step(nsteps, dt, scheme, **TIGHT32)
+    assert rep["converged"] == 1, rep
+    fo = implicit.implicit_step(o, scheme, nsteps, dt, f0)
+    assert _rel(g.get_state(), fo) < TOL, (name, scheme, rep)
+
+
+def test_fp32_basis_deterministic_and_reaches_steady_state():
+    _say("[gpu] implicit FP32 basis: determinism, steady state")
+    spec = workloads.cavity(n=8, p=2, m=8, lid=0.1, kn=1.0)
+    runs = []
+    for _ in range(2):
+        g = binding.Solver.from_spec(spec)
+        g.init_equilibrium()
+        r0 = g.residual()
+        dt = 5000 * g.stable_dt(0.2)
+        res = []
+        for _ in range(6):
+            rep = g.implicit_step(1, dt, "backward_euler", max_krylov=1000, krylov_rtol=1e-5,
+                                  krylov_fp32=True)
+            assert rep["converged"] == 1, rep
+            res.append(g.residual())
+        runs.append((g.get_state(), res))
+    _say(f"  residuals {r0:.3e} -> {[f'{r:.2e}' for r in runs[0][1]]}")
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[0][1][-1] < 1e-6 * r0
+
+
 def test_implicit_step_is_deterministic():
     _say("[gpu] implicit determinism")
     spec = workloads.cavity(n=12, p=3, m=8, lid=0.1)
