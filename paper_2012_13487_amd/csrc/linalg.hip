@@ -54,9 +54,7 @@ __device__ inline double block_sum(double v, double *red) {
 
 // Work-group (g, j) sums V_k . w for k = kVecs j ... kVecs j + kVecs - 1 over
 // the chunks g, g + G, g + 2G, ... of kBlock * kItems elements.
-// T: element type of the basis.  SELF: vector nv is w itself (w . w).
-template <typename T, bool SELF>
-__global__ __launch_bounds__(kBlock) void multi_dot_partial_kernel(size_t n, int nv, const T *V,
+__global__ __launch_bounds__(kBlock) void multi_dot_partial_kernel(size_t n, int nv, const double *V,
                                                                    size_t vstride, const double *w,
                                                                    double *partial) {
   __shared__ double red[kBlock / 64];
@@ -65,17 +63,68 @@ __global__ __launch_bounds__(kBlock) void multi_dot_partial_kernel(size_t n, int
   double acc[kVecs];
 #pragma unroll
   for (int t = 0; t < kVecs; ++t) acc[t] = 0.0;
-  const size_t chunk = (size_t)kBlock * kItems;
+  // two consecutive elements per access (16-byte loads)
+  const size_t chunk = (size_t)kBlock * kItems * 2;
   for (size_t base = (size_t)blockIdx.x * chunk; base < n; base += (size_t)G * chunk) {
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
-      const size_t i = base + (size_t)it * kBlock + threadIdx.x;
-      if (i < n) {
+      const size_t i = base + 2 * ((size_t)it * kBlock + threadIdx.x);
+      if (i + 1 < n) {
+        const double2 wi = *reinterpret_cast<const double2 *>(w + i);
+#pragma unroll
+        for (int t = 0; t < kVecs; ++t)
+          if (k0 + t < nv) {
+            const double2 v = *reinterpret_cast<const double2 *>(V + (size_t)(k0 + t) * vstride + i);
+            acc[t] += v.x * wi.x + v.y * wi.y;
+          }
+      } else if (i < n) {
+        const double wi = w[i];
+#pragma unroll
+        for (int t = 0; t < kVecs; ++t)
+          if (k0 + t < nv) acc[t] += V[(size_t)(k0 + t) * vstride + i] * wi;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kVecs; ++t) {
+    const double s = block_sum(acc[t], red);
+    if (threadIdx.x == 0 && k0 + t < nv) partial[(size_t)(k0 + t) * G + blockIdx.x] = s;
+  }
+}
+
+// The FP32-basis form: as above with two consecutive elements per access
+// (float2 basis loads, double2 loads of w), and vector nv taken as w itself.
+__global__ __launch_bounds__(kBlock) void multi_dot32_partial_kernel(size_t n, int nv, const float *V,
+                                                                     size_t vstride, const double *w,
+                                                                     double *partial) {
+  __shared__ double red[kBlock / 64];
+  const int k0 = blockIdx.y * kVecs;
+  const int G = gridDim.x;
+  double acc[kVecs];
+#pragma unroll
+  for (int t = 0; t < kVecs; ++t) acc[t] = 0.0;
+  const size_t chunk = (size_t)kBlock * kItems * 2;
+  for (size_t base = (size_t)blockIdx.x * chunk; base < n; base += (size_t)G * chunk) {
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const size_t i = base + 2 * ((size_t)it * kBlock + threadIdx.x);
+      if (i + 1 < n) {
+        const double2 wi = *reinterpret_cast<const double2 *>(w + i);
+#pragma unroll
+        for (int t = 0; t < kVecs; ++t) {
+          if (k0 + t < nv) {
+            const float2 v = *reinterpret_cast<const float2 *>(V + (size_t)(k0 + t) * vstride + i);
+            acc[t] += (double)v.x * wi.x + (double)v.y * wi.y;
+          } else if (k0 + t == nv) {
+            acc[t] += wi.x * wi.x + wi.y * wi.y;
+          }
+        }
+      } else if (i < n) {
         const double wi = w[i];
 #pragma unroll
         for (int t = 0; t < kVecs; ++t) {
           if (k0 + t < nv) acc[t] += (double)V[(size_t)(k0 + t) * vstride + i] * wi;
-          else if (SELF && k0 + t == nv) acc[t] += wi * wi;
+          else if (k0 + t == nv) acc[t] += wi * wi;
         }
       }
     }
@@ -83,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void multi_dot_partial_kernel(size_t n, int
 #pragma unroll
   for (int t = 0; t < kVecs; ++t) {
     const double s = block_sum(acc[t], red);
-    if (threadIdx.x == 0 && k0 + t < nv + (SELF ? 1 : 0)) partial[(size_t)(k0 + t) * G + blockIdx.x] = s;
+    if (threadIdx.x == 0 && k0 + t <= nv) partial[(size_t)(k0 + t) * G + blockIdx.x] = s;
   }
 }
 
@@ -98,19 +147,66 @@ __global__ __launch_bounds__(kBlock) void multi_dot_final_kernel(int G, const do
   if (threadIdx.x == 0) result[blockIdx.x] = s;
 }
 
-// out32 (optional): an FP32 copy of out.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void multi_axpy_kernel(size_t n, int nv, const T *V,
+// Two consecutive elements per thread (16-byte loads).
+__global__ __launch_bounds__(kBlock) void multi_axpy_kernel(size_t n, int nv, const double *V,
                                                             size_t vstride, const double *coef,
                                                             double alpha, const double *w,
-                                                            double scale, double *out, float *out32) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    double s = 0.0;
-    for (int k = 0; k < nv; ++k) s += coef[k] * (double)V[(size_t)k * vstride + i];
-    const double r = scale * (w[i] + alpha * s);
-    out[i] = r;
-    if (out32) out32[i] = (float)r;
+                                                            double scale, double *out) {
+  const size_t stride = 2 * (size_t)gridDim.x * blockDim.x;
+  for (size_t i = 2 * ((size_t)blockIdx.x * blockDim.x + threadIdx.x); i < n; i += stride) {
+    if (i + 1 < n) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int k = 0; k < nv; ++k) {
+        const double2 v = *reinterpret_cast<const double2 *>(V + (size_t)k * vstride + i);
+        s0 += coef[k] * v.x;
+        s1 += coef[k] * v.y;
+      }
+      const double2 wi = *reinterpret_cast<const double2 *>(w + i);
+      double2 r;
+      r.x = scale * (wi.x + alpha * s0);
+      r.y = scale * (wi.y + alpha * s1);
+      *reinterpret_cast<double2 *>(out + i) = r;
+    } else {
+      double s0 = 0.0;
+      for (int k = 0; k < nv; ++k) s0 += coef[k] * V[(size_t)k * vstride + i];
+      out[i] = scale * (w[i] + alpha * s0);
+    }
+  }
+}
+
+// The FP32-basis form, two consecutive elements per thread (float2 basis
+// loads); out32 (optional) receives out rounded to FP32.
+__global__ __launch_bounds__(kBlock) void multi_axpy32_kernel(size_t n, int nv, const float *V,
+                                                              size_t vstride, const double *coef,
+                                                              double alpha, const double *w,
+                                                              double scale, double *out, float *out32) {
+  const size_t stride = 2 * (size_t)gridDim.x * blockDim.x;
+  for (size_t i = 2 * ((size_t)blockIdx.x * blockDim.x + threadIdx.x); i < n; i += stride) {
+    if (i + 1 < n) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int k = 0; k < nv; ++k) {
+        const float2 v = *reinterpret_cast<const float2 *>(V + (size_t)k * vstride + i);
+        s0 += coef[k] * (double)v.x;
+        s1 += coef[k] * (double)v.y;
+      }
+      const double2 wi = *reinterpret_cast<const double2 *>(w + i);
+      double2 r;
+      r.x = scale * (wi.x + alpha * s0);
+      r.y = scale * (wi.y + alpha * s1);
+      *reinterpret_cast<double2 *>(out + i) = r;
+      if (out32) {
+        float2 r32;
+        r32.x = (float)r.x;
+        r32.y = (float)r.y;
+        *reinterpret_cast<float2 *>(out32 + i) = r32;
+      }
+    } else {
+      double s0 = 0.0;
+      for (int k = 0; k < nv; ++k) s0 += coef[k] * (double)V[(size_t)k * vstride + i];
+      const double r = scale * (w[i] + alpha * s0);
+      out[i] = r;
+      if (out32) out32[i] = (float)r;
+    }
   }
 }
 
@@ -142,10 +238,10 @@ size_t multi_dot_scratch(size_t n, int nv) { return (size_t)dot_groups(n) * (siz
 hipError_t launch_multi_dot(size_t n, int nv, const double *V, size_t vstride, const double *w,
                             double *scratch, double *result, hipStream_t st) {
   if (nv < 1 || nv > kMaxBasis) return hipErrorInvalidValue;
-  const int G = dot_groups(n);
+  const int G = dot_groups((n + 1) / 2);  // within multi_dot_scratch(n, nv)
   const unsigned gy = (unsigned)((nv + kVecs - 1) / kVecs);
-  hipLaunchKernelGGL((multi_dot_partial_kernel<double, false>), dim3((unsigned)G, gy), dim3(kBlock), 0,
-                     st, n, nv, V, vstride, w, scratch);
+  hipLaunchKernelGGL(multi_dot_partial_kernel, dim3((unsigned)G, gy), dim3(kBlock), 0, st, n, nv, V,
+                     vstride, w, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(multi_dot_final_kernel, dim3((unsigned)nv), dim3(kBlock), 0, st, G, scratch,
@@ -158,8 +254,8 @@ hipError_t launch_multi_axpy(size_t n, int nv, const double *V, size_t vstride, 
                              hipStream_t st) {
   if (nv < 0 || nv > kMaxBasis) return hipErrorInvalidValue;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(multi_axpy_kernel<double>, dim3(stream_blocks(n)), dim3(kBlock), 0, st, n, nv, V,
-                     vstride, coef, alpha, w, scale, out, (float *)nullptr);
+  hipLaunchKernelGGL(multi_axpy_kernel, dim3(stream_blocks((n + 1) / 2)), dim3(kBlock), 0, st, n, nv,
+                     V, vstride, coef, alpha, w, scale, out);
   return hipGetLastError();
 }
 
@@ -174,11 +270,13 @@ hipError_t launch_lincomb_mixed(size_t n, double a, const double *x, double b, c
 hipError_t launch_multi_dot32(size_t n, int nv, const float *V, size_t vstride, const double *w,
                               double *scratch, double *result, hipStream_t st) {
   if (nv < 0 || nv + 1 > kMaxBasis) return hipErrorInvalidValue;
-  const int G = dot_groups(n);
+  // half the groups of the FP64 form (two elements per access): within
+  // the scratch that multi_dot_scratch(n, nv + 1) sizes
+  const int G = dot_groups((n + 1) / 2);
   const int nt = nv + 1;
   const unsigned gy = (unsigned)((nt + kVecs - 1) / kVecs);
-  hipLaunchKernelGGL((multi_dot_partial_kernel<float, true>), dim3((unsigned)G, gy), dim3(kBlock), 0,
-                     st, n, nv, V, vstride, w, scratch);
+  hipLaunchKernelGGL(multi_dot32_partial_kernel, dim3((unsigned)G, gy), dim3(kBlock), 0, st, n, nv, V,
+                     vstride, w, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(multi_dot_final_kernel, dim3((unsigned)nt), dim3(kBlock), 0, st, G, scratch,
@@ -191,8 +289,8 @@ hipError_t launch_multi_axpy32(size_t n, int nv, const float *V, size_t vstride,
                                hipStream_t st) {
   if (nv < 0 || nv > kMaxBasis) return hipErrorInvalidValue;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(multi_axpy_kernel<float>, dim3(stream_blocks(n)), dim3(kBlock), 0, st, n, nv, V,
-                     vstride, coef, alpha, w, scale, out, out32);
+  hipLaunchKernelGGL(multi_axpy32_kernel, dim3(stream_blocks((n + 1) / 2)), dim3(kBlock), 0, st, n, nv,
+                     V, vstride, coef, alpha, w, scale, out, out32);
   return hipGetLastError();
 }
 
