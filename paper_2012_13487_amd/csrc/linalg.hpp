@@ -1,6 +1,9 @@
 // Vector kernels of the implicit (Newton-Krylov) time step.  Every
 // reduction has a fixed assignment of elements to work-groups and a fixed
 // summation order for a given length, so results are bitwise reproducible.
+// The multi-dot and multi-axpy kernels take two consecutive elements per
+// access: their FP64 vectors must be 16-byte aligned, FP32 basis vectors
+// (base and stride) 8-byte aligned.
 #pragma once
 
 #include <hip/hip_runtime.h>
