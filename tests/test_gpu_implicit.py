@@ -168,18 +168,20 @@ def test_large_backward_euler_steps_reach_steady_state():
     assert all(res[i + 1] < res[i] for i in range(len(res) - 1))
 
 
-def test_full_size_backward_euler_satisfies_its_equation(oracle_mod):
+@pytest.mark.parametrize("basis", [dict(), dict(krylov_fp32=True, krylov_rtol=1e-5)],
+                         ids=["fp64_basis", "fp32_basis"])
+def test_full_size_backward_euler_satisfies_its_equation(oracle_mod, basis):
     """Lid-driven cavity 64 x 64, p = 3, NC 16 x 16: one backward-Euler step
-    of 10 explicit step sizes; the result y must satisfy
-    y - f0 - dt L(y) = 0 with L the oracle's right-hand side, and conserve
-    mass."""
+    of 10 explicit step sizes (Krylov basis in FP64, and in FP32); the result
+    y must satisfy y - f0 - dt L(y) = 0 with L the oracle's right-hand side,
+    and conserve mass."""
     spec = workloads.CAVITY_64x64_P3_NC16
-    _say(f"[gpu] implicit full size {spec.name}")
+    _say(f"[gpu] implicit full size {spec.name} {basis}")
     g = binding.Solver.from_spec(spec)
     f0 = workloads.perturbed_state(6, g.w, g.K, g.Np, amp=0.05)
     g.set_state(f0)
     dt = 10 * g.stable_dt(0.2)
-    rep = g.implicit_step(1, dt, "backward_euler", newton_rtol=1e-12)
+    rep = g.implicit_step(1, dt, "backward_euler", newton_rtol=1e-12, **basis)
     _say(f"  report {rep}")
     assert rep["converged"] == 1, rep
     y = g.get_state()
