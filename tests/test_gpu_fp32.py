@@ -7,11 +7,13 @@ workload also checks the FP64 path in its velocity-tiled form (bar 1e-12).
 
 Bars: FP32 storage, 1e-5 relative in max-norm on rho and u (normwise over
 nodes and components for u, as in the FP64 tests) after the same RK4 steps
-and on the right-hand side itself.  bf16 contractions, 2e-3 on rho and u;
-on the right-hand side 4e-3: both factors of the products Dr g, Ds g are
+and on the right-hand side itself.  bf16 contractions, 2e-3 on rho and u
+and on the right-hand side: both factors of the products Dr g, Ds g are
 rounded to bf16 (unit roundoff 2^-9 each) after the row mean is subtracted,
-so the volume term carries about 2 x 2^-9 relative to the in-element
-variation of g, which is at most the size of the right-hand side here."""
+so the volume term carries up to about 2 x 2^-9 = 3.9e-3 relative to the
+in-element variation of g in the worst case; the rounding errors of the
+products' terms are independent and partly cancel, and 2e-3 is the bar the
+path is held to."""
 import sys
 
 import numpy as np
@@ -25,7 +27,7 @@ pytestmark = pytest.mark.gpu
 TOL64 = 1e-12  # the FP64 path's bar
 TOL32 = 1e-5
 TOL_BF = 2e-3
-TOL_BF_RHS = 4e-3
+TOL_BF_RHS = 2e-3
 
 
 def _say(*a):
