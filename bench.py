@@ -5,7 +5,11 @@ nodes per element), Newton-Cotes 16 x 16 velocities on [-4,4]^2, Kn = 1,
 lid speed 0.1, diffuse walls, FP64, explicit RK4 at CFL 0.2 -- 16.8 M
 degrees of freedom (nodes x velocities).  One step = one RK4 step (four
 fused stage kernels); the steady-state residual is evaluated on the device
-every 50 steps inside the timed region.
+inside the timed region after every 50 steps (--resid-every), so a run of
+fewer steps evaluates none.  Before the W warm-up steps the solver steps for
+--settle-s seconds untimed: the GPU's clocks ramp for about 40 steps after an
+idle period (stage launches run at 115-122 us instead of 104 us), and the
+timed region should see the steady device, as a solve of 1e5 steps does.
 
 Prints one JSON line with the metric, a roofline object for the stage kernel
 (its average duration measured with HIP events on the stream it runs on), the
@@ -27,8 +31,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 ALG_BYTES_PER_DOF_STAGE = 32.0  # FP64 RK4, 3 registers: 24/40/40/24 B per stage -> 32 mean
-# FP32 increment-form RK4: 12/20/20/16 B per stage -> 17 mean
+# FP32 increment-form RK4: 12/20/20/16 B per stage -> 17 mean (what the
+# kernels move); the method's own FP32 figure (3 registers) is 16 B
 ALG_BYTES_PER_DOF_STAGE_FP32 = 17.0
+ALG_BYTES_PER_DOF_STAGE_FP32_METHOD = 16.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_cavity64x64_p3_nc16_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2012_13487_amd", "csrc", "kernels.hip")
 
@@ -51,29 +57,46 @@ def measured_traffic():
     return t.get("hbm_bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(spec, budget_s):
-    """The FP64 oracle on the host's cores, on a bounded number of RK4 steps."""
+    """The FP64 oracle on the host's cores, on a bounded number of RK4 steps;
+    then on one thread, on a smaller bounded sample of the same workload."""
     import oracle
-    import workloads
 
     threads = max(1, min(16, len(os.sched_getaffinity(0))))
-    oracle.set_threads(threads)
     o = oracle.Oracle.from_spec(spec)
-    o.init_equilibrium()
     dt = o.stable_dt(spec.cfl)
-    t0 = time.perf_counter()
-    o.rk4(1, dt)
-    one = time.perf_counter() - t0
-    n = max(1, min(50, int(budget_s / max(one, 1e-9)) - 1))
-    t0 = time.perf_counter()
-    o.rk4(n, dt)
-    el = time.perf_counter() - t0
     dof = o.Q * o.K * o.Np
-    del workloads
-    return {"value": dof * 4 * n / el, "unit": "DOF-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+
+    def rate(nthreads, budget, cap):
+        oracle.set_threads(nthreads)
+        o.init_equilibrium()
+        t0 = time.perf_counter()
+        o.rk4(1, dt)
+        one = time.perf_counter() - t0
+        n = max(1, min(cap, int(budget / max(one, 1e-9)) - 1))
+        t0 = time.perf_counter()
+        o.rk4(n, dt)
+        return dof * 4 * n / (time.perf_counter() - t0), n, oracle.num_threads()
+
+    v, n, used = rate(threads, budget_s, 50)
+    v1, n1, _ = rate(1, budget_s / 3, 10)
+    return {"value": v, "unit": "DOF-updates/s", "cores": used, "kind": "oracle",
             "sample": f"{n} RK4 steps ({4 * n} stages) of the same {dof}-DOF cavity workload, "
-                      f"FP64 C oracle, OpenMP over elements"}
+                      f"FP64 C oracle, OpenMP over elements",
+            "single_thread": {"value": v1, "unit": "DOF-updates/s", "cores": 1,
+                              "sample": f"{n1} RK4 steps of the same workload on one thread"},
+            "cpu_model": cpu_model(), "host_cpus_visible": len(os.sched_getaffinity(0))}
 
 
 def time_steps(solver, steps, dt):
@@ -116,6 +139,10 @@ def precision_path(steps_small, steps_big):
                            "avg_launch_us": stage_us, "alg_bytes_per_dof_stage": bpd,
                            "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS, "steps": steps,
                            "tiling": g.tiling()}
+            if prec != "fp64":
+                # the method's 3-register FP32 figure, beside the increment form's
+                m = ALG_BYTES_PER_DOF_STAGE_FP32_METHOD * g.ndof / (stage_us * 1e-6) / 1e9
+                entry[prec]["frac_at_16B_per_dof_stage"] = m / HBM_PEAK_GBS
             g.close()
         out[key] = entry
     big = out["cavity128x128_p4_nc24_kn8"]
@@ -295,6 +322,75 @@ def implicit_path(steps=2, mult=10.0, race_target=1e-6):
     return out
 
 
+def couette_config1(repeats=5):
+    """The plain-method Couette workload (8x8 quads, p=2, D2Q16, Kn=1, 200 RK4
+    steps from rest, 9,216 DOF): launch-bound, so timed with ordinary launches
+    and with the steps replayed from a captured hipGraph (50 steps per graph),
+    each the median of `repeats` 200-step solves."""
+    import workloads
+    from paper_2012_13487_amd import Solver
+
+    spec = workloads.COUETTE_8x8_P2_D2Q16
+    out = {"workload": "Couette [0,1]^2, walls +-0.1, 8x8 quads p=2, D2Q16 Gauss-Hermite, Kn=1 "
+                       "(tau = Kn/sqrt(pi/2)), FP64 RK4 CFL 0.2, 200 steps from rest",
+           "steps": spec.steps}
+    for name, k in (("eager", 0), ("graph", 50)):
+        g = Solver.from_spec(spec, stream="torch", torch_memory=True)
+        g.set_graph(k)
+        dt = g.stable_dt(spec.cfl)
+        g.init_equilibrium()
+        g.step(spec.steps, dt)  # warm-up (and the graph capture)
+        times = []
+        for _ in range(repeats):
+            g.init_equilibrium()
+            times.append(_timed(lambda: g.step(spec.steps, dt)))
+        ms = sorted(times)[len(times) // 2]
+        out[name] = {"value": g.ndof * 4 * spec.steps / (ms / 1000.0), "unit": "DOF-updates/s",
+                     "ms_per_solve": ms, "us_per_stage": 1000.0 * ms / (4 * spec.steps),
+                     "steps_per_graph": k, "tiling": g.tiling()}
+        out["dof"] = g.ndof
+        g.close()
+    out["graph_over_eager"] = out["graph"]["value"] / out["eager"]["value"]
+    return out
+
+
+def converge(resid_every, max_steps, target=1e-6):
+    """The benchmark cavity (64x64 quads, p=3, NC 16x16, Kn=1, FP64) from rest
+    to residual `target`: RK4 steps and device time, the residual evaluated on
+    the device every `resid_every` steps (its launches are in the time)."""
+    import torch
+
+    import workloads
+    from paper_2012_13487_amd import Solver
+
+    spec = workloads.CAVITY_64x64_P3_NC16
+    g = Solver.from_spec(spec, stream="torch", torch_memory=True)
+    dt = g.stable_dt(spec.cfl)
+    g.init_equilibrium()
+    resid = torch.zeros(1, dtype=torch.float64, device="cuda")
+    history = []
+    steps = 0
+    t0 = time.perf_counter()
+    r = g.residual()
+    history.append((0, r))
+    while r >= target and steps < max_steps:
+        g.step(resid_every, dt)
+        steps += resid_every
+        g.residual_async(resid.data_ptr())
+        r = float(resid.item())
+        if steps % (50 * resid_every) == 0 or r < target:
+            history.append((steps, r))
+            print(f"converge: step {steps} residual {r:.3e} "
+                  f"elapsed {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    return {"workload": "lid-driven cavity 64x64 quads p=3, NC 16x16 velocities on [-4,4]^2, Kn=1, "
+                        "lid 0.1, diffuse walls, FP64 RK4 CFL 0.2, from rest",
+            "target": target, "converged": r < target, "steps": steps, "residual": r,
+            "dt": dt, "simulated_time": steps * dt, "wall_s": wall,
+            "dof_updates_per_s": g.ndof * 4 * steps / wall, "residual_every": resid_every,
+            "history": history}
+
+
 def _timed(fn):
     """Milliseconds of the device work `fn` enqueues on torch's current stream."""
     import torch
@@ -316,6 +412,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--resid-every", type=int, default=50)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--settle-s", type=float, default=1.0,
+                    help="seconds of untimed steps before the warm-up (clock ramp)")
+    ap.add_argument("--converge", action="store_true",
+                    help="only run the benchmark cavity from rest to residual 1e-6 and "
+                         "report steps and time")
+    ap.add_argument("--no-couette", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-path", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
@@ -345,6 +447,9 @@ def main():
         print(json.dumps({"calibration": "device copy", "bytes_read": x.numel() * 8,
                           "bytes_written": x.numel() * 8, "launches": 5}), flush=True)
         return
+    if args.converge:
+        print(json.dumps({"converge": converge(1000, 3_000_000)}), flush=True)
+        return
     spec = workloads.CAVITY_64x64_P3_NC16
     g = Solver.from_spec(spec, stream="torch", torch_memory=True)
     dt = g.stable_dt(spec.cfl)
@@ -352,6 +457,14 @@ def main():
     g.init_equilibrium()
     resid = torch.zeros(max(1, args.steps // max(1, args.resid_every)) + 1,
                         dtype=torch.float64, device="cuda")
+    settle_steps = 0
+    if args.settle_s > 0:
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < args.settle_s:
+            g.step(20, dt)
+            settle_steps += 20
+            torch.cuda.synchronize()
+        g.init_equilibrium()  # the timed steps start from rest, as without settling
     if args.warmup:
         g.step(args.warmup, dt)
     stream = torch.cuda.current_stream()
@@ -405,6 +518,7 @@ def main():
             "dof": dof, "elements": g.K, "nodes_per_element": g.Np, "velocities": g.Q,
             "dt": dt, "residual_every": args.resid_every,
             "residual_last": res[-1] if res else None,
+            "device_settle_steps": settle_steps,
         },
         "roofline": {
             "bound": "hbm",
@@ -420,6 +534,8 @@ def main():
         "cpu_baseline": None,
     }
     del g
+    if not args.no_couette:
+        out["couette_config1"] = couette_config1()
     if not args.no_precision_path:
         out["precision_path"] = precision_path(100, 20)
     if not args.no_batching:

@@ -132,7 +132,12 @@ int dgbgk_create(const dgbgk_problem *pb, int32_t precision, void *hip_stream,
  * Must precede the first device call. */
 int dgbgk_bind_buffers(dgbgk_solver *s, void *device_ptr, size_t bytes);
 
-/* Replace the stream used by later calls. */
+/* Replace the stream used by later calls.  Work the solver enqueues on the new
+ * stream is ordered after all work it enqueued before on the old stream (an
+ * event recorded on the old stream is waited on by the new one), so a switch
+ * right after dgbgk_step() needs no host synchronisation; the call itself does
+ * not block the host.  The caller keeps the new stream alive while the solver
+ * uses it. */
 int dgbgk_set_stream(dgbgk_solver *s, void *hip_stream);
 
 void dgbgk_destroy(dgbgk_solver *s);
@@ -189,6 +194,17 @@ int dgbgk_state_device_ptr(dgbgk_solver *s, void **ptr);
  *            - (f_q - f_q^eq(rho, u)) / tau  (collision)
  * with rho, u and the diffuse-wall densities taken from the stage state. */
 int dgbgk_step(dgbgk_solver *s, int64_t nsteps, double dt);
+
+/* Replay RK4 steps from a captured hipGraph: with steps_per_graph = k > 0,
+ * dgbgk_step() captures k steps (for the current dt and work decomposition)
+ * once, on a capture stream of the library's own, and then enqueues
+ * nsteps / k graph launches on the solver's stream plus the remaining steps
+ * as ordinary launches; a change of dt or of the work decomposition
+ * re-captures (after waiting for replays in flight).  Results are
+ * bit-identical to eager steps.  For problems so small that launch overhead,
+ * not HBM bandwidth, bounds a stage.  0 (the default) turns replay off.
+ * k in 0..1000; DGBGK_EINVAL otherwise. */
+int dgbgk_set_graph(dgbgk_solver *s, int32_t steps_per_graph);
 
 /* Evaluate the right-hand side L(f) for a host state f (count = Q*K*Np) into
  * a host array k; the solver's own state is left unchanged.  Synchronises. */

@@ -102,6 +102,7 @@ SIGNATURES = {
     "dgbgk_get_state": (C.c_int, [C.c_void_p, _dp, C.c_size_t]),
     "dgbgk_state_device_ptr": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "dgbgk_step": (C.c_int, [C.c_void_p, C.c_int64, C.c_double]),
+    "dgbgk_set_graph": (C.c_int, [C.c_void_p, C.c_int32]),
     "dgbgk_rhs": (C.c_int, [C.c_void_p, _dp, _dp, C.c_size_t]),
     "dgbgk_implicit_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_double,
                                       C.POINTER(ImplicitOptions), C.POINTER(ImplicitReport)]),
@@ -374,6 +375,11 @@ class Solver:
 
     def step(self, nsteps, dt):
         self._call("dgbgk_step", int(nsteps), float(dt))
+
+    def set_graph(self, steps_per_graph):
+        """Replay steps_per_graph RK4 steps at a time from a captured hipGraph
+        (0: ordinary launches)."""
+        self._call("dgbgk_set_graph", int(steps_per_graph))
 
     def implicit_step(self, nsteps, dt, scheme="backward_euler", max_newton=20, newton_rtol=1e-10,
                       newton_atol=1e-14, restart=30, max_krylov=300, krylov_rtol=1e-6,

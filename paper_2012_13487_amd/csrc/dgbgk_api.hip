@@ -110,6 +110,12 @@ struct dgbgk_solver {
   size_t lds = 0;
   int tiling_mode = 0, tiling_qt = 0;
   int forced_E = 0;  // elements per work-group set by the caller or the autotuner (0: automatic)
+  // RK4 steps replayed from a captured hipGraph (0: eager launches)
+  int graph_steps = 0;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;  // capture stream (the solver's may be the null stream)
+  double graph_dt = 0.0;             // dt and launch configuration the graph was captured with
+  int graph_cfg[5] = {0, 0, 0, 0, 0};
   // implicit-step workspace (allocated at the first implicit step)
   double *imp_ws = nullptr;
   size_t imp_bytes = 0;
@@ -647,12 +653,28 @@ int dgbgk_bind_buffers(dgbgk_solver *s, void *device_ptr, size_t bytes) {
 
 int dgbgk_set_stream(dgbgk_solver *s, void *hip_stream) {
   if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
-  s->stream = (hipStream_t)hip_stream;
+  hipStream_t ns = (hipStream_t)hip_stream;
+  if (ns != s->stream && s->dev_ready) {
+    // work enqueued on the new stream must not overtake the stages still in
+    // flight on the old one (they read and write the same registers)
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, s->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ns, ev, 0);
+    if (ev) (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return hip_fail(s, e, "ordering the new stream after the old one");
+  }
+  s->stream = ns;
   return DGBGK_OK;
 }
 
 void dgbgk_destroy(dgbgk_solver *s) {
   if (!s) return;
+  if (s->gexec) {
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipGraphExecDestroy(s->gexec);
+  }
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->owns && s->base) {
     (void)hipStreamSynchronize(s->stream);
     (void)hipFree(s->base);
@@ -837,20 +859,105 @@ int dgbgk_state_device_ptr(dgbgk_solver *s, void **ptr) {
   return DGBGK_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One RK4 step.  Registers: f_n, acc, and two stage buffers A/B so that a
+// stage never overwrites the state its neighbours still read.
+int enqueue_rk4_step(dgbgk_solver *s, double dt) {
+  int rc;
+  void *fn = s->d_fn, *A = s->d_a, *B = s->d_b;
+  if ((rc = run_stage(s, 1, fn, A, dt))) return rc;
+  if ((rc = run_stage(s, 2, A, B, dt))) return rc;
+  if ((rc = run_stage(s, 3, B, A, dt))) return rc;
+  return run_stage(s, 4, A, fn, dt);
+}
+
+void drop_solver_graph(dgbgk_solver *s) {
+  if (s->gexec) {
+    (void)hipStreamSynchronize(s->stream);  // replays in flight still use it
+    (void)hipGraphExecDestroy(s->gexec);
+  }
+  s->gexec = nullptr;
+}
+
+// Captures graph_steps RK4 steps of size dt on the capture stream.
+int capture_solver_graph(dgbgk_solver *s, double dt) {
+  drop_solver_graph(s);
+  hipError_t e = hipSuccess;
+  if (!s->cap_stream) e = hipStreamCreate(&s->cap_stream);
+  if (e != hipSuccess) return hip_fail(s, e, "capture stream");
+  // the capture stream starts after the solver's stream (set-up work on it)
+  hipEvent_t ev = nullptr;
+  e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ev, s->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s->cap_stream, ev, 0);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->cap_stream);
+  if (ev) (void)hipEventDestroy(ev);
+  if (e != hipSuccess) return hip_fail(s, e, "capture stream ordering");
+  hipStream_t own = s->stream;
+  s->stream = s->cap_stream;
+  e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+  int rc = DGBGK_OK;
+  if (e == hipSuccess)
+    for (int i = 0; i < s->graph_steps && !rc; ++i) rc = enqueue_rk4_step(s, dt);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(s->cap_stream, &g) : e;
+  s->stream = own;
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e2 == hipSuccess) e2 = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) {
+    s->gexec = nullptr;
+    return hip_fail(s, e2, "graph capture");
+  }
+  s->graph_dt = dt;
+  const int cfg[5] = {s->fused, s->E, s->Qt, s->persistent, s->prec};
+  std::memcpy(s->graph_cfg, cfg, sizeof cfg);
+  return DGBGK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dgbgk_set_graph(dgbgk_solver *s, int32_t steps_per_graph) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (steps_per_graph < 0 || steps_per_graph > 1000)
+    return fail(s, DGBGK_EINVAL, "steps_per_graph must be in 0..1000");
+  if (steps_per_graph != s->graph_steps) drop_solver_graph(s);
+  s->graph_steps = steps_per_graph;
+  return DGBGK_OK;
+}
+
 int dgbgk_step(dgbgk_solver *s, int64_t nsteps, double dt) {
   if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
   if (nsteps < 0 || !(dt > 0) || !is_finite_d(dt)) return fail(s, DGBGK_EINVAL, "need nsteps >= 0, dt > 0");
   if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
   int rc = ensure_device(s);
   if (rc) return rc;
-  for (int64_t it = 0; it < nsteps; ++it) {
-    // registers: f_n, acc, and two stage buffers A/B so that a stage never
-    // overwrites the state its neighbours still read.
-    void *fn = s->d_fn, *A = s->d_a, *B = s->d_b;
-    if ((rc = run_stage(s, 1, fn, A, dt))) return rc;
-    if ((rc = run_stage(s, 2, A, B, dt))) return rc;
-    if ((rc = run_stage(s, 3, B, A, dt))) return rc;
-    if ((rc = run_stage(s, 4, A, fn, dt))) return rc;
+  int64_t it = 0;
+  if (s->graph_steps > 0 && nsteps >= s->graph_steps) {
+    const int cfg[5] = {s->fused, s->E, s->Qt, s->persistent, s->prec};
+    if (!s->gexec || s->graph_dt != dt || std::memcmp(cfg, s->graph_cfg, sizeof cfg) != 0) {
+      // one eager step first: it sets the kernels' LDS attributes outside the capture
+      if ((rc = enqueue_rk4_step(s, dt))) return rc;
+      ++s->steps;
+      ++it;
+      if ((rc = capture_solver_graph(s, dt))) return rc;
+    }
+    for (; it + s->graph_steps <= nsteps; it += s->graph_steps) {
+      hipError_t e = hipGraphLaunch(s->gexec, s->stream);
+      if (e != hipSuccess) return hip_fail(s, e, "graph launch");
+      s->steps += s->graph_steps;
+    }
+  }
+  for (; it < nsteps; ++it) {
+    if ((rc = enqueue_rk4_step(s, dt))) return rc;
     ++s->steps;
   }
   return DGBGK_OK;

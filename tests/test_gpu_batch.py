@@ -1,8 +1,10 @@
 """Batched execution on the GPU: several problems (mixed meshes, orders,
 velocity sets, Kn, walls and precisions) advanced by persistent batched
 kernels.  Each member's result must be bit-identical to the same solver
-stepped alone (batch invariance), with and without hipGraph replay; the
-autotuner must keep results within the FP64 bar against the oracle."""
+stepped alone (batch invariance), with and without hipGraph replay, and
+within its precision's bar of the FP64 oracle (1e-12 FP64, 1e-5 FP32
+storage, 2e-3 bf16 contractions); the autotuner must keep results within the
+FP64 bar against the oracle."""
 import sys
 
 import numpy as np
@@ -32,7 +34,12 @@ MEMBERS = [
     (workloads.cavity(n=3, ny=5, p=3, m=7, lid=0.05, kn=0.7), binding.FP64),
     (workloads.couette(nx=4, ny=4, p=2, kn=2.0), binding.FP64),
     (workloads.cavity(n=5, ny=3, p=3, m=10, lid=0.2), binding.FP32),
+    (workloads.cavity(n=3, ny=4, p=4, m=8, lid=0.1, kn=0.6), binding.FP32),
+    (workloads.cavity(n=4, ny=3, p=4, m=6, lid=0.15, kn=1.5), binding.FP32_BF16MMA),
 ]
+
+# bars against the FP64 oracle per precision
+TOLS = {binding.FP64: 1e-12, binding.FP32: 1e-5, binding.FP32_BF16MMA: 2e-3}
 
 
 def _make(seed_base=100):
@@ -62,6 +69,32 @@ def test_batch_members_match_solo(graph):
     for i, (gb, gs) in enumerate(zip(members, solo)):
         assert gb.steps_taken() == 15
         assert np.array_equal(gb.get_state(), gs.get_state()), MEMBERS[i][0].name
+    b.close()
+
+
+def test_batch_members_match_oracle(oracle_mod):
+    """Every member of the mixed batch (FP64, FP32 and bf16 members, fused p = 4
+    members among them) after 15 hipGraph-replayed batched RK4 steps, against
+    the oracle stepped from the same state with the member's own dt."""
+    _say("[gpu] batch vs oracle")
+    members = _make()
+    dts = _dts(members)
+    for (spec, prec), g in zip(MEMBERS, members):
+        if spec.p == 4:
+            assert g.tiling()["fused"] == 1, spec.name
+    b = binding.Batch(members, graph=True)
+    b.step(15, dts)
+    for i, ((spec, prec), g) in enumerate(zip(MEMBERS, members)):
+        o = oracle_mod.Oracle.from_spec(spec)
+        o.set_state(workloads.perturbed_state(100 + i, o.w, o.K, o.Np, amp=0.05))
+        o.rk4(15, dts[i])
+        ro, uxo, uyo = o.moments()
+        rg, uxg, uyg = g.moments()
+        er = float(np.max(np.abs(rg - ro)) / np.max(np.abs(ro)))
+        u_o = np.stack([uxo, uyo])
+        eu = float(np.max(np.abs(np.stack([uxg, uyg]) - u_o)) / np.max(np.abs(u_o)))
+        _say(f"  {spec.name} prec {prec}: err rho {er:.2e} u {eu:.2e}")
+        assert er < TOLS[prec] and eu < TOLS[prec], (spec.name, prec, er, eu)
     b.close()
 
 

@@ -58,6 +58,12 @@ RHS_CASES = [
     # one element per block (20 columns, strips of 16), two (20 blocks of 2, strips of 8)
     ("cavity_20x3_p2_nc16_strips_E1", workloads.cavity(n=20, ny=3, p=2, m=16, lid=0.1), None),
     ("cavity_40x2_p3_nc10_strips_E2", workloads.cavity(n=40, ny=2, p=3, m=10, lid=0.1), None),
+    # the fused forms at higher orders (the tiles of small p = 4 batch and
+    # serving members, and orders 6 and 7, which the ABI accepts)
+    ("cavity_6x5_p4_nc6_fused", workloads.cavity(n=6, ny=5, p=4, m=6, lid=0.1), None),
+    ("cavity_5x4_p4_nc12_fused", workloads.cavity(n=5, ny=4, p=4, m=12, lid=0.15, kn=0.4), None),
+    ("cavity_4x3_p6_nc5_fused", workloads.cavity(n=4, ny=3, p=6, m=5, lid=0.1), None),
+    ("couette_3x2_p7_gh4_fused", workloads.couette(nx=3, ny=2, p=7), None),
 ]
 
 
@@ -120,6 +126,28 @@ def test_strip_ordered_blocks_steps_match_oracle(oracle_mod, name, spec, tiling)
     assert _rel(g.get_state(), o.get_state()) < TOL
 
 
+FUSED_HIGH_ORDER = [c for c in RHS_CASES if c[0].endswith("_fused")]
+
+
+@pytest.mark.parametrize("name,spec,tiling", FUSED_HIGH_ORDER, ids=[c[0] for c in FUSED_HIGH_ORDER])
+def test_fused_high_order_steps_match_oracle(oracle_mod, name, spec, tiling):
+    """20 RK4 steps of a perturbed state in the automatic (fused) form at
+    p = 4, 6 and 7 against the oracle."""
+    _say(f"[gpu] fused high order, 20 steps: {name}")
+    g, o = _pair(oracle_mod, spec, tiling)
+    assert g.tiling()["fused"] == 1
+    f = workloads.perturbed_state(37, o.w, o.K, o.Np, amp=0.05)
+    g.set_state(f)
+    o.set_state(f)
+    dt = o.stable_dt(0.2)
+    g.step(20, dt)
+    o.rk4(20, dt)
+    er, eu = _moment_errors(g, o)
+    _say(f"  err rho {er:.2e} u {eu:.2e}")
+    assert er < TOL and eu < TOL, (er, eu)
+    assert _rel(g.get_state(), o.get_state()) < TOL
+
+
 @pytest.mark.parametrize("tiling", [None, (2, 13), (4, 0)])
 def test_cavity_perturbed_steps_match_oracle(oracle_mod, tiling):
     _say(f"[gpu] cavity 10x7 p3 nc10 perturbed, tiling={tiling}")
@@ -134,6 +162,49 @@ def test_cavity_perturbed_steps_match_oracle(oracle_mod, tiling):
     er, eu = _moment_errors(g, o)
     assert er < TOL and eu < TOL, (er, eu)
     assert _rel(g.get_state(), o.get_state()) < TOL
+
+
+@pytest.mark.parametrize("name,spec,tiling", [
+    ("couette_8x8_p2_gh4", workloads.COUETTE_8x8_P2_D2Q16, None),
+    ("cavity_5x3_p4_nc6_tiled", workloads.cavity(n=5, ny=3, p=4, m=6, lid=0.2), (2, 7)),
+    ("cavity_9x7_p3_nc9_persistent", workloads.cavity(n=9, ny=7, p=3, m=9, lid=0.15), (4, 0))],
+    ids=["couette_8x8_p2_gh4", "cavity_5x3_p4_nc6_tiled", "cavity_9x7_p3_nc9_persistent"])
+def test_graph_replayed_steps_identical_to_eager(oracle_mod, name, spec, tiling):
+    """dgbgk_set_graph: steps replayed from a captured hipGraph, with step counts
+    that are not multiples of the graph length, a change of dt (re-capture) and
+    a change of block size (re-capture), bit-identical to ordinary launches and
+    within the FP64 bar of the oracle."""
+    _say(f"[gpu] graph-replayed steps: {name}")
+    a, o = _pair(oracle_mod, spec, tiling)
+    b = binding.Solver.from_spec(spec)
+    if tiling is not None:
+        b.set_tiling(*tiling)
+    b.set_graph(7)
+    f = workloads.perturbed_state(43, o.w, o.K, o.Np, amp=0.05)
+    for g in (a, b):
+        g.set_state(f)
+    o.set_state(f)
+    dt0 = o.stable_dt(0.2)
+    total = 0
+    for n, dt in ((20, dt0), (3, dt0), (15, 0.5 * dt0), (14, 0.5 * dt0)):
+        a.step(n, dt)
+        b.step(n, dt)
+        o.rk4(n, dt)
+        total += n
+        assert np.array_equal(a.get_state(), b.get_state()), (n, dt)
+        assert b.steps_taken() == total
+    er, eu = _moment_errors(b, o)
+    assert er < TOL and eu < TOL, (er, eu)
+    if tiling is None:
+        for g in (a, b):
+            g.set_block_elements(1)
+        a.step(9, dt0)
+        b.step(9, dt0)
+        assert np.array_equal(a.get_state(), b.get_state())
+    b.set_graph(0)
+    a.step(2, dt0)
+    b.step(2, dt0)
+    assert np.array_equal(a.get_state(), b.get_state())
 
 
 def test_fused_and_tiled_agree():
@@ -252,6 +323,26 @@ def test_stream_switch_and_device_state_view():
     fa, fb = a.get_state(), b.get_state()
     b.set_stream(None)  # the side stream may go away before b does
     assert np.array_equal(fa, fb)
+
+    # a switch while steps are still in flight on the old stream: the new
+    # stream's work is ordered after them (no host synchronisation between)
+    big = workloads.cavity(n=32, p=3, m=16, lid=0.1)
+    c = binding.Solver.from_spec(big)
+    d = binding.Solver.from_spec(big)
+    dtb = c.stable_dt(0.2)
+    c.init_equilibrium()
+    c.step(50, dtb)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    d.set_stream(s1.cuda_stream)
+    d.init_equilibrium()
+    d.step(40, dtb)
+    d.set_stream(s2.cuda_stream)
+    d.step(10, dtb)
+    fc, fd = c.get_state(), d.get_state()
+    d.set_stream(None)
+    assert np.array_equal(fc, fd)
+    c.close()
+    d.close()
 
     # copy the device state out with the HIP runtime the process has loaded
     import ctypes

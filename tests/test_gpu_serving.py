@@ -3,7 +3,9 @@ request must end below the residual target, and its result must be the same
 alone and in the mix (bit for bit: each request's steps and checks depend only
 on its own residual history); the memory budget must bound the requests on
 the device; the mixed-precision server (FP32 storage, finished in FP64) must
-reach the same target."""
+reach the same target; every served result must match the FP64 oracle run
+from rest for the same number of RK4 steps (1e-12 for FP64, 1e-5 for FP32
+storage finished in FP64)."""
 import sys
 
 import numpy as np
@@ -81,3 +83,28 @@ def test_admission_bounded_by_memory():
     for a, b in zip(mom, mref):
         for x, y in zip(a, b):
             assert np.array_equal(x, y)
+
+
+def _oracle_errors(oracle_mod, spec, steps, moments):
+    o = oracle_mod.Oracle.from_spec(spec)
+    o.init_equilibrium()
+    o.rk4(steps, o.stable_dt(0.2))
+    ro, uxo, uyo = o.moments()
+    rg, uxg, uyg = (m.reshape(ro.shape) for m in moments)
+    er = float(np.max(np.abs(rg - ro)) / np.max(np.abs(ro)))
+    u_o = np.stack([uxo, uyo])
+    eu = float(np.max(np.abs(np.stack([uxg, uyg]) - u_o)) / np.max(np.abs(u_o)))
+    return er, eu
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_served_results_match_oracle(oracle_mod, precision, tol):
+    """Each request of the mix, served to residual 1e-6, against the oracle
+    run from rest (f = w) for exactly the request's RK4 steps at the same dt."""
+    _say(f"[gpu] served {precision} results vs oracle")
+    res, mom, _ = _serve(REQS, ARRIVALS, precision=precision)
+    for req, r, m in zip(REQS, res, mom):
+        assert r["status"] == binding.REQ_CONVERGED
+        er, eu = _oracle_errors(oracle_mod, req, r["steps"], m)
+        _say(f"  {req.name}: {r['steps']} steps: err rho {er:.2e} u {eu:.2e}")
+        assert er < tol and eu < tol, (req.name, er, eu)
