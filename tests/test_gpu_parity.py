@@ -110,7 +110,10 @@ def test_couette_200_steps_matches_oracle(oracle_mod):
     assert g.steps_taken() == spec.steps
 
 
-@pytest.mark.parametrize("name,spec,tiling", RHS_CASES[-2:], ids=[c[0] for c in RHS_CASES[-2:]])
+STRIP_CASES = [c for c in RHS_CASES if "_strips_" in c[0]]
+
+
+@pytest.mark.parametrize("name,spec,tiling", STRIP_CASES, ids=[c[0] for c in STRIP_CASES])
 def test_strip_ordered_blocks_steps_match_oracle(oracle_mod, name, spec, tiling):
     _say(f"[gpu] strip-ordered blocks, 20 steps: {name}")
     g, o = _pair(oracle_mod, spec, tiling)
