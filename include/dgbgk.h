@@ -331,6 +331,23 @@ typedef struct {
 int dgbgk_implicit_step(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double dt,
                         const dgbgk_implicit_options *opt, dgbgk_implicit_report *report);
 
+/* For callers that cannot allocate device memory (serving loops and harnesses
+ * that forbid hipMalloc): dgbgk_implicit_step with the same arguments, results
+ * and errors, except that it allocates nothing.  Its device workspace is a
+ * static array of the library, 64 MiB (67108864 bytes) per device, of which
+ * a call needs about (restart + stages + 6) x 8 K Np Q bytes (FP32 basis:
+ * (restart + 1) x 4 K Np Q of them in FP32); a call that needs more returns
+ * DGBGK_EINVAL without touching the state.  The solver must already hold a
+ * state (its device memory exists) and its device must be current
+ * (DGBGK_ESTATE / DGBGK_EDEVICE otherwise).  Every call on one device
+ * shares that device's array and overwrites it: calls that overlap in time on
+ * one device (other host threads, other solvers) race and must be
+ * serialised by the caller.  Each device the library runs on holds its array
+ * until the process ends. */
+int dgbgk_implicit_step_noalloc(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double dt,
+                                const dgbgk_implicit_options *opt,
+                                dgbgk_implicit_report *report);
+
 /* ---- batches: several problems advanced together ------------------------
  *
  * A batch advances n solvers (any mix of meshes, orders, velocity sets, Kn,

@@ -106,6 +106,9 @@ SIGNATURES = {
     "dgbgk_rhs": (C.c_int, [C.c_void_p, _dp, _dp, C.c_size_t]),
     "dgbgk_implicit_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_double,
                                       C.POINTER(ImplicitOptions), C.POINTER(ImplicitReport)]),
+    "dgbgk_implicit_step_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_double,
+                                              C.POINTER(ImplicitOptions),
+                                              C.POINTER(ImplicitReport)]),
     "dgbgk_wall_density": (C.c_int, [C.c_void_p, _dp, _dp, C.c_size_t]),
     "dgbgk_residual": (C.c_int, [C.c_void_p, _dp]),
     "dgbgk_residual_async": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -383,14 +386,17 @@ class Solver:
 
     def implicit_step(self, nsteps, dt, scheme="backward_euler", max_newton=20, newton_rtol=1e-10,
                       newton_atol=1e-14, restart=30, max_krylov=300, krylov_rtol=1e-6,
-                      krylov_fp32=False):
+                      krylov_fp32=False, noalloc=False):
         """nsteps SDIRK steps (Newton with matrix-free GMRES); returns the report as a dict.
-        krylov_fp32: store the Krylov basis in FP32 (needs krylov_rtol >= 1e-5)."""
+        krylov_fp32: store the Krylov basis in FP32 (needs krylov_rtol >= 1e-5).
+        noalloc: the allocation-free entry point (workspace in the library's
+        static 64 MiB per-device array)."""
         sc = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
         o = ImplicitOptions(int(max_newton), float(newton_rtol), float(newton_atol), int(restart),
                             int(max_krylov), float(krylov_rtol), int(krylov_fp32))
         r = ImplicitReport()
-        self._call("dgbgk_implicit_step", sc, int(nsteps), float(dt), C.byref(o), C.byref(r))
+        self._call("dgbgk_implicit_step_noalloc" if noalloc else "dgbgk_implicit_step", sc,
+                   int(nsteps), float(dt), C.byref(o), C.byref(r))
         return {name: getattr(r, name) for name, _ in ImplicitReport._fields_}
 
     def rhs(self, f):

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -91,6 +92,7 @@ struct dgbgk_solver {
   hipStream_t stream = nullptr;
   // device
   bool dev_ready = false;
+  int device = -1;  // the device holding the solver's memory
   void *base = nullptr;
   bool owns = false;
   Layout lay{};
@@ -264,6 +266,7 @@ int ensure_device(dgbgk_solver *s) {
     return fail(s, DGBGK_EDEVICE, "device %d is %s; this library is built for gfx950", dev,
                 prop.gcnArchName);
   if (prop.multiProcessorCount > 0) s->num_cu = prop.multiProcessorCount;
+  s->device = dev;
   if (s->lds > prop.sharedMemPerBlock && s->lds > 65536)
     return fail(s, DGBGK_EDEVICE, "stage kernel needs %zu B of LDS, device allows %zu", s->lds,
                 (size_t)prop.sharedMemPerBlock);
@@ -1617,10 +1620,47 @@ struct Implicit {
 
 }  // namespace
 
-extern "C" {
+// Static workspace of the allocation-free implicit step: one array per device
+// (each device that runs the library holds its own copy until the process
+// ends).  Host code never passes the array's name to a kernel: its device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current.
+constexpr size_t kStaticWsBytes = (size_t)64 << 20;
+static __device__ __align__(256) double scratch[kStaticWsBytes / sizeof(double)];
 
-int dgbgk_implicit_step(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double dt,
-                        const dgbgk_implicit_options *opt, dgbgk_implicit_report *report) {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the static workspace on the solver's device (which must
+// be current).
+int static_workspace(dgbgk_solver *s, double **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(s, e, "hipGetDevice");
+  if (dev != s->device)
+    return fail(s, DGBGK_EDEVICE, "device %d is current; the solver's memory is on device %d", dev,
+                s->device);
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(s, DGBGK_EDEVICE, "device %d: the static workspace covers devices 0..%d", dev,
+                kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(s, e, "hipGetSymbolAddress(static workspace)");
+    if (!p || (uintptr_t)p % kAlign) return fail(s, DGBGK_EDEVICE, "static workspace address %p", p);
+    g_scratch_ptr[dev] = (double *)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DGBGK_OK;
+}
+
+int implicit_steps(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double dt,
+                   const dgbgk_implicit_options *opt, dgbgk_implicit_report *report,
+                   bool static_ws) {
   if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
   Sdirk tab;
   if (!sdirk_tableau(scheme, tab)) return fail(s, DGBGK_EINVAL, "unknown implicit scheme %d", scheme);
@@ -1636,16 +1676,27 @@ int dgbgk_implicit_step(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double 
     return fail(s, DGBGK_EINVAL, "an FP32 Krylov basis needs krylov_rtol >= 1e-5");
   if (s->prec != DGBGK_FP64) return fail(s, DGBGK_ENOTSUP, "implicit steps need FP64 precision");
   if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
+  // a state implies the solver's device memory exists (nothing is allocated here)
+  if (static_ws && !s->dev_ready) return fail(s, DGBGK_ESTATE, "solver has no device memory");
   int rc = ensure_device(s);
   if (rc) return rc;
-  if (report) *report = dgbgk_implicit_report{0, 0, 0, 0.0, 1};
 
   Implicit im{s, ImplicitWs{}, o.restart};
   const size_t n = (size_t)s->K * s->Np * s->Q;
   size_t stride = 0;
   const bool v32 = o.krylov_fp32 != 0;
   const size_t bytes = implicit_ws_bytes(n, tab.stages, im.m, v32, &stride);
-  if (bytes > s->imp_bytes) {
+  double *ws = nullptr;
+  if (static_ws) {
+    if (bytes > kStaticWsBytes)
+      return fail(s, DGBGK_EINVAL,
+                  "implicit workspace of %zu B exceeds the %zu B static workspace (a shorter "
+                  "GMRES restart, the FP32 Krylov basis or a smaller problem fits)",
+                  bytes, kStaticWsBytes);
+    if ((rc = static_workspace(s, &ws))) return rc;
+  }
+  if (report) *report = dgbgk_implicit_report{0, 0, 0, 0.0, 1};
+  if (!static_ws && bytes > s->imp_bytes) {
     if (s->imp_ws) {
       (void)hipStreamSynchronize(s->stream);
       (void)hipFree(s->imp_ws);
@@ -1658,10 +1709,11 @@ int dgbgk_implicit_step(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double 
     s->imp_ws = (double *)p;
     s->imp_bytes = bytes;
   }
+  if (!static_ws) ws = s->imp_ws;
   ImplicitWs &w = im.w;
   w.n = n;
   w.stride = stride;
-  double *q = s->imp_ws;
+  double *q = ws;
   w.K = q;  q += (size_t)tab.stages * stride;
   w.y = q;  q += stride;
   w.b = q;  q += stride;
@@ -1741,6 +1793,20 @@ int dgbgk_implicit_step(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double 
     report->converged = all_conv ? 1 : 0;
   }
   return DGBGK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dgbgk_implicit_step(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double dt,
+                        const dgbgk_implicit_options *opt, dgbgk_implicit_report *report) {
+  return implicit_steps(s, scheme, nsteps, dt, opt, report, false);
+}
+
+int dgbgk_implicit_step_noalloc(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double dt,
+                                const dgbgk_implicit_options *opt, dgbgk_implicit_report *report) {
+  return implicit_steps(s, scheme, nsteps, dt, opt, report, true);
 }
 
 }  // extern "C"
