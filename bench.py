@@ -354,7 +354,7 @@ def couette_config1(repeats=5):
     return out
 
 
-def converge(resid_every, max_steps, target=1e-6):
+def converge(resid_every, max_steps, max_s, target=1e-6):
     """The benchmark cavity (64x64 quads, p=3, NC 16x16, Kn=1, FP64) from rest
     to residual `target`: RK4 steps and device time, the residual evaluated on
     the device every `resid_every` steps (its launches are in the time)."""
@@ -373,7 +373,7 @@ def converge(resid_every, max_steps, target=1e-6):
     t0 = time.perf_counter()
     r = g.residual()
     history.append((0, r))
-    while r >= target and steps < max_steps:
+    while r >= target and steps < max_steps and time.perf_counter() - t0 < max_s:
         g.step(resid_every, dt)
         steps += resid_every
         g.residual_async(resid.data_ptr())
@@ -417,6 +417,7 @@ def main():
     ap.add_argument("--converge", action="store_true",
                     help="only run the benchmark cavity from rest to residual 1e-6 and "
                          "report steps and time")
+    ap.add_argument("--converge-max-s", type=float, default=1000.0)
     ap.add_argument("--no-couette", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-path", action="store_true")
@@ -448,7 +449,7 @@ def main():
                           "bytes_written": x.numel() * 8, "launches": 5}), flush=True)
         return
     if args.converge:
-        print(json.dumps({"converge": converge(1000, 3_000_000)}), flush=True)
+        print(json.dumps({"converge": converge(1000, 3_000_000, args.converge_max_s)}), flush=True)
         return
     spec = workloads.CAVITY_64x64_P3_NC16
     g = Solver.from_spec(spec, stream="torch", torch_memory=True)
