@@ -75,9 +75,32 @@ typedef enum { DGBGK_BC_PERIODIC = 0, DGBGK_BC_DIFFUSE_WALL = 1 } dgbgk_bc;
  *   DGBGK_FP32_BF16MMA: as DGBGK_FP32, with the volume term's contractions
  *     Dr g, Ds g on bf16 matrix cores with FP32 accumulation (DGBGK_ENOTSUP
  *     where this build has no such kernel).
+ *   DGBGK_FP32_REF: the reference form.  The state is f = f_r + g with an FP64
+ *     reference f_r (not streamed by the stages) and an FP32 correction g in
+ *     the RK registers.  The transport part of the right-hand side (volume
+ *     term, upwind jumps, and the diffuse-wall exterior state, whose density
+ *     of eq. (8) is linear in the outgoing values) is linear, so
+ *     L(f_r + g) = L(f_r) + T(g) - g/tau + [f^eq(m_r + m_g) - f^eq(m_r)]/tau
+ *     (eq. (5), (6); m = node moments): L(f_r) is evaluated in FP64 when the
+ *     reference is set and streamed in FP32, the node moments are reduced in
+ *     FP64, and the difference of equilibria is formed from the moment
+ *     increments with FP64 node factors.  Every FP32 quantity is then
+ *     rounded relative to the correction or to the current rate, which both
+ *     vanish at a steady state, so the path reaches the steady-state
+ *     residuals FP64 reaches while streaming FP32 (plus L(f_r): 21 bytes per
+ *     DOF and stage on average against 32 for FP64).  dgbgk_fold() moves g
+ *     into f_r; a caller folds from time to time (e.g. at every residual
+ *     check) to keep g small.  p <= 4.
+ *   DGBGK_FP32_BF16MMA_REF: the reference form with the bf16 contractions.
  * The FP32 precisions run only the fused form (all velocities of an element
  * in one work-group); create returns DGBGK_ENOTSUP when that does not fit. */
-typedef enum { DGBGK_FP64 = 0, DGBGK_FP32 = 1, DGBGK_FP32_BF16MMA = 2 } dgbgk_precision;
+typedef enum {
+  DGBGK_FP64 = 0,
+  DGBGK_FP32 = 1,
+  DGBGK_FP32_BF16MMA = 2,
+  DGBGK_FP32_REF = 3,
+  DGBGK_FP32_BF16MMA_REF = 4
+} dgbgk_precision;
 
 /* Problem statement (Sec. II: mesh and polynomial order, velocity set and
  * weights, relaxation time, wall and lid conditions). */
@@ -185,7 +208,8 @@ int dgbgk_get_state(dgbgk_solver *s, double *f, size_t count);
 
 /* Device address of the current state, element-major f[k][q][n] (FP64,
  * Q*K*Np doubles; for the FP32 precisions the FP32 deviation g[k][q][n] =
- * f - w_q), valid until the next dgbgk_step(); for zero-copy views. */
+ * f - w_q; for the reference forms the FP32 correction g = f - f_r), valid
+ * until the next dgbgk_step(); for zero-copy views. */
 int dgbgk_state_device_ptr(dgbgk_solver *s, void **ptr);
 
 /* Advance nsteps classical RK4 steps of size dt (enqueued; returns at once).
@@ -207,11 +231,14 @@ int dgbgk_step(dgbgk_solver *s, int64_t nsteps, double dt);
 int dgbgk_set_graph(dgbgk_solver *s, int32_t steps_per_graph);
 
 /* Evaluate the right-hand side L(f) for a host state f (count = Q*K*Np) into
- * a host array k; the solver's own state is left unchanged.  Synchronises. */
+ * a host array k; the solver's own state is left unchanged.  Synchronises.
+ * The reference forms evaluate it as a correction f - f_r to the solver's
+ * current reference (DGBGK_ESTATE before init / set_state). */
 int dgbgk_rhs(dgbgk_solver *s, const double *f, double *k, size_t count);
 
 /* Diffuse-wall densities (eq. (8)) of a host state f at every face node,
- * out[K][4][Nfp]; entries of non-wall faces are 0.  Synchronises. */
+ * out[K][4][Nfp]; entries of non-wall faces are 0.  Synchronises.
+ * DGBGK_ENOTSUP for the reference forms. */
 int dgbgk_wall_density(dgbgk_solver *s, const double *f, double *out, size_t count);
 
 /* Steady-state residual of the current state:
@@ -229,6 +256,11 @@ int dgbgk_residual_async(dgbgk_solver *s, double *device_out);
  * u = sum_q e_q f_q / rho; host arrays of K*Np.  Synchronises; returns
  * DGBGK_ENONFINITE if any value is not finite. */
 int dgbgk_moments(dgbgk_solver *s, double *rho, double *ux, double *uy);
+
+/* Reference forms: f_r += g, g = 0, then L(f_r) and the moments of f_r are
+ * re-evaluated (FP64).  Enqueued; the state f is unchanged (up to the FP64
+ * rounding of the sum).  DGBGK_ENOTSUP for the other precisions. */
+int dgbgk_fold(dgbgk_solver *s);
 
 /* Wait for all work enqueued by s. */
 int dgbgk_synchronize(dgbgk_solver *s);
@@ -376,17 +408,19 @@ typedef struct dgbgk_batch dgbgk_batch;
 int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream,
                        dgbgk_batch **out);
 
-/* use_graph != 0: each RK4 step of the batch is captured once in a hipGraph
- * and replayed (re-captured when the membership changes, not when dt does:
- * the descriptors are device data). */
+/* use_graph = k > 0: k RK4 steps of the batch are captured once in a hipGraph
+ * and replayed (plus a one-step graph for the remainder of a call;
+ * re-captured when the membership changes, not when dt does: the descriptors
+ * are device data).  0: ordinary launches.  k in 0..1000. */
 int dgbgk_batch_set_graph(dgbgk_batch *b, int32_t use_graph);
 
 /* nsteps RK4 steps of every member; dt[i] is member i's time step (n values,
  * host array).  Enqueues only.  Every member needs a state (DGBGK_ESTATE). */
 int dgbgk_batch_step(dgbgk_batch *b, int64_t nsteps, const double *dt);
 
-/* Steady-state residual of every member (as dgbgk_residual) into r[n]
- * (host); synchronises.  Non-finite residuals are returned as NaN and the
+/* Steady-state residual of every member (as dgbgk_residual, bit for bit) into
+ * r[n] (host): one right-hand-side launch per class, one reduction per member,
+ * one copy to the host; synchronises.  Non-finite residuals are returned as NaN and the
  * call returns DGBGK_ENONFINITE after filling all entries. */
 int dgbgk_batch_residuals(dgbgk_batch *b, double *r);
 
@@ -418,7 +452,10 @@ void dgbgk_batch_destroy(dgbgk_batch *b);
  * below polish_below or stops falling (less than 10% lower than its best over
  * 20 checks), then its state moves to an FP64 solver that finishes the solve
  * (FP32 storage cannot reach residuals much below 1e-5: its rounding floor).
- * The device memory of such a request is reserved at the FP64 size. */
+ * The device memory of such a request is reserved at the FP64 size.  With a
+ * reference form (DGBGK_FP32_REF, DGBGK_FP32_BF16MMA_REF) a request runs in
+ * that precision to the end, its correction folded into the FP64 reference
+ * after every residual check (polish_below is ignored). */
 typedef struct dgbgk_server dgbgk_server;
 
 typedef struct {

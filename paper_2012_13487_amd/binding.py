@@ -14,8 +14,9 @@ LIB_PATH = os.path.join(HERE, "libdgbgk.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
 BC_PERIODIC, BC_DIFFUSE_WALL = 0, 1
-FP64, FP32, FP32_BF16MMA = 0, 1, 2
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_bf16mma": FP32_BF16MMA}
+FP64, FP32, FP32_BF16MMA, FP32_REF, FP32_BF16MMA_REF = 0, 1, 2, 3, 4
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp32_bf16mma": FP32_BF16MMA, "fp32_ref": FP32_REF,
+              "fp32_bf16mma_ref": FP32_BF16MMA_REF}
 
 _dp = C.POINTER(C.c_double)
 
@@ -114,6 +115,7 @@ SIGNATURES = {
     "dgbgk_residual_async": (C.c_int, [C.c_void_p, C.c_void_p]),
     "dgbgk_moments": (C.c_int, [C.c_void_p, _dp, _dp, _dp]),
     "dgbgk_synchronize": (C.c_int, [C.c_void_p]),
+    "dgbgk_fold": (C.c_int, [C.c_void_p]),
     "dgbgk_set_tiling": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "dgbgk_get_tiling": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                    C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]),
@@ -247,8 +249,8 @@ class Solver:
 
     ``stream``: a HIP stream handle (int) or "torch" for torch's current
     stream; ``torch_memory``: take device memory from a torch tensor;
-    ``precision``: FP64, FP32 or FP32_BF16MMA (or "fp64", "fp32",
-    "fp32_bf16mma")."""
+    ``precision``: FP64, FP32, FP32_BF16MMA, FP32_REF or FP32_BF16MMA_REF (or
+    "fp64", "fp32", "fp32_bf16mma", "fp32_ref", "fp32_bf16mma_ref")."""
 
     def __init__(self, nx, ny, p, velset, tau, bc, wall_u, x0=0.0, y0=0.0, lx=1.0, ly=1.0,
                  stream=None, torch_memory=False, precision=FP64):
@@ -429,6 +431,10 @@ class Solver:
     def synchronize(self):
         self._call("dgbgk_synchronize")
 
+    def fold(self):
+        """Reference forms: move the FP32 correction into the FP64 reference."""
+        self._call("dgbgk_fold")
+
     def steps_taken(self):
         s = C.c_int64()
         self._call("dgbgk_steps_taken", C.byref(s))
@@ -452,10 +458,12 @@ class Batch:
                                          C.byref(h)))
         self._h = h.value
         if graph:
-            self.set_graph(True)
+            self.set_graph(graph)
 
-    def set_graph(self, on):
-        _bcheck(lib().dgbgk_batch_set_graph(self._h, int(bool(on))), self._h)
+    def set_graph(self, steps_per_graph):
+        """Replay steps_per_graph RK4 steps at a time from a captured hipGraph
+        (True: one step; 0 / False: ordinary launches)."""
+        _bcheck(lib().dgbgk_batch_set_graph(self._h, int(steps_per_graph)), self._h)
 
     def step(self, nsteps, dt):
         dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64),
@@ -496,7 +504,8 @@ class Server:
             import torch  # plumbing only: the stream
             stream = torch.cuda.current_stream().cuda_stream
         if polish_below is None:  # FP32 precisions: finish in FP64 below 15 x the target
-            polish_below = 0.0 if _prec(precision) == FP64 else 15.0 * residual_target
+            polish_below = (0.0 if _prec(precision) in (FP64, FP32_REF, FP32_BF16MMA_REF)
+                            else 15.0 * residual_target)
         opt = ServerOptions(int(hbm_budget), int(max_active), _prec(precision),
                             float(residual_target), int(check_every), int(max_steps), float(cfl),
                             int(bool(graph)), float(polish_below))

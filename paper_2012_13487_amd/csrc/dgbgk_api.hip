@@ -40,10 +40,16 @@ constexpr size_t kLastLevelCacheBytes = (size_t)256 << 20;
 int stream_nt_for(size_t state_bytes) { return 4 * state_bytes > kLastLevelCacheBytes ? 1 : 0; }
 
 struct Layout {
-  size_t fn, acc, a, b, xfer, vel, feqb, wmom, dmat, mom, rhow, u64, total;
+  size_t fn, acc, a, b, xfer, vel, feqb, wmom, dmat, mom, rhow, u64, fref, rref, mref, total;
 };
 
-bool is_fp32(int precision) { return precision == DGBGK_FP32 || precision == DGBGK_FP32_BF16MMA; }
+bool is_fp32(int precision) {
+  return precision == DGBGK_FP32 || precision == DGBGK_FP32_BF16MMA || precision == DGBGK_FP32_REF ||
+         precision == DGBGK_FP32_BF16MMA_REF;
+}
+bool is_bf(int precision) { return precision == DGBGK_FP32_BF16MMA || precision == DGBGK_FP32_BF16MMA_REF; }
+bool is_ref(int precision) { return precision == DGBGK_FP32_REF || precision == DGBGK_FP32_BF16MMA_REF; }
+bool valid_precision(int precision) { return precision == DGBGK_FP64 || is_fp32(precision); }
 
 // State registers (FP64, or the FP32 deviation), an FP64 transfer buffer for
 // the FP32 precisions, then the small tables.
@@ -64,6 +70,11 @@ Layout make_layout(int64_t K, int Np, int Nfp, int Q, int precision) {
   L.rhow = off; off += round_up((size_t)K * 4 * Nfp * sizeof(double));
   L.u64 = off;  off += round_up(8 * sizeof(unsigned long long));
   L.dmat = off; off += round_up((size_t)((2 * Np + 15) / 16) * 16 * 32 * sizeof(uint16_t));
+  // reference form: the FP64 reference state, its right-hand side in FP32 and its node moments
+  const bool ref = is_ref(precision);
+  L.fref = off; off += ref ? round_up(ndof * sizeof(double)) : 0;
+  L.rref = off; off += ref ? round_up(ndof * sizeof(float)) : 0;
+  L.mref = off; off += ref ? round_up((size_t)3 * K * Np * sizeof(double)) : 0;
   L.total = off;
   return L;
 }
@@ -105,6 +116,13 @@ struct dgbgk_solver {
   double mconst[7] = {0, 0, 0, 0, 0, 0, 0};
   double *d_vel = nullptr, *d_feqb = nullptr, *d_wmom = nullptr, *d_mom = nullptr, *d_rhow = nullptr;
   unsigned long long *d_u64 = nullptr;
+  // reference form: f = f_ref + g (FP64 reference, FP32 correction in the registers)
+  double *d_fref = nullptr, *d_mref = nullptr;
+  float *g_rref = nullptr;
+  struct Cfg64 {
+    int fused = 1, E = 1, log2E = 0, Qt = 0, ntiles = 1, nblk = 1;
+    size_t lds = 0;
+  } ref64;  // FP64 decomposition of the reference's right-hand side
   // launch configuration
   int fused = 1, E = 1, log2E = 0, Qt = 0, ntiles = 1, nblk = 1;
   int persistent = 0;  // fused blocks run by the persistent pipelined kernel
@@ -190,10 +208,10 @@ constexpr int64_t kMaxBlockDof = 4096;
 
 void choose_tiling32(dgbgk_solver *s) {
   const int NP = s->Np;
-  const bool bf = s->prec == DGBGK_FP32_BF16MMA;
+  const bool bf = is_bf(s->prec), ref = is_ref(s->prec);
   int E = 1;
   while ((int64_t)E * 2 * s->Q * NP <= kMaxBlockDof && E * 2 <= s->K &&
-         stage32_lds_bytes(s->p, E * 2, s->Q, bf) <= kFusedLdsLimit)
+         stage32_lds_bytes(s->p, E * 2, s->Q, bf, ref) <= kFusedLdsLimit)
     E *= 2;
   if (s->forced_E > 0) E = s->forced_E;
   s->E = E;
@@ -204,7 +222,7 @@ void choose_tiling32(dgbgk_solver *s) {
   s->Qt = s->Q;
   s->ntiles = 1;
   s->nblk = (int)((s->K + E - 1) / E);
-  s->lds = stage32_lds_bytes(s->p, E, s->Q, bf);
+  s->lds = stage32_lds_bytes(s->p, E, s->Q, bf, ref);
 }
 
 // Launch configuration: fused (all velocities of E elements per work-group)
@@ -295,6 +313,11 @@ int ensure_device(dgbgk_solver *s) {
   s->d_mom = (double *)(b + s->lay.mom);
   s->d_rhow = (double *)(b + s->lay.rhow);
   s->d_u64 = (unsigned long long *)(b + s->lay.u64);
+  if (is_ref(s->prec)) {
+    s->d_fref = (double *)(b + s->lay.fref);
+    s->g_rref = (float *)(b + s->lay.rref);
+    s->d_mref = (double *)(b + s->lay.mref);
+  }
   std::vector<double> vel((size_t)3 * s->Q);
   for (int q = 0; q < s->Q; ++q) {
     vel[q] = s->ex[q];
@@ -324,7 +347,7 @@ int ensure_device(dgbgk_solver *s) {
     e = hipMemcpyAsync(s->d_feqb, s->feqb.data(), s->feqb.size() * sizeof(double),
                        hipMemcpyHostToDevice, s->stream);
   std::vector<uint16_t> dm;
-  if (s->prec == DGBGK_FP32_BF16MMA) {
+  if (is_bf(s->prec)) {
     // [Dr; Ds] (2 Np x Np, node n = i + N1 j), rows padded to 16-row tiles and
     // columns to 32, rounded to bf16 (nearest, ties to even)
     const int N1 = s->Nfp, Np = s->Np, rows = (2 * Np + 15) / 16 * 16;
@@ -403,7 +426,9 @@ Stage32Args base_args32(const dgbgk_solver *s) {
   a.vel = s->d_vel;
   a.feqb = s->d_feqb;
   a.wmom = s->d_wmom;
-  a.dmat = s->prec == DGBGK_FP32_BF16MMA ? s->d_dmat : nullptr;
+  a.dmat = is_bf(s->prec) ? s->d_dmat : nullptr;
+  a.rref = is_ref(s->prec) ? s->g_rref : nullptr;
+  a.mref = is_ref(s->prec) ? s->d_mref : nullptr;
   a.rx = (float)(2.0 / s->hx);
   a.sy = (float)(2.0 / s->hy);
   a.fsx = (float)(2.0 / s->hx);
@@ -453,7 +478,7 @@ int run_stage32(dgbgk_solver *s, int stage, const float *fs, float *out, double 
   rk_coefficients(stage, dt, ca, co);
   a.c_acc = (float)ca;
   a.c_out = (float)co;
-  hipError_t e = launch_stage32(s->p, a, s->lds, s->prec == DGBGK_FP32_BF16MMA, s->stream);
+  hipError_t e = launch_stage32(s->p, a, s->lds, is_bf(s->prec), is_ref(s->prec), s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "FP32 stage kernel");
   return DGBGK_OK;
 }
@@ -490,6 +515,53 @@ int run_stage(dgbgk_solver *s, int stage, const void *fs_, void *out_, double dt
   }
   if (e != hipSuccess) return hip_fail(s, e, "stage kernel");
   return DGBGK_OK;
+}
+
+// Reference form: r = L(f_ref) by the FP64 stage kernel (into the FP64
+// transfer buffer, then rounded to FP32), and the node moments of f_ref.
+int ref_refresh(dgbgk_solver *s) {
+  const dgbgk_solver::Cfg64 &c = s->ref64;
+  const int K = (int)s->K;
+  const size_t KN = (size_t)s->K * s->Np, n = KN * s->Q;
+  hipError_t e = hipSuccess;
+  if (!c.fused)
+    e = launch_moments(s->d_fref, s->d_vel, K, s->p, s->Q, s->pb.nx, s->pb.ny, s->wall_mask,
+                       s->wall_den_inv, s->d_mom, s->d_mom + KN, s->d_mom + 2 * KN,
+                       s->wall_mask ? s->d_rhow : nullptr, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "reference moments pass");
+  StageArgs a = base_args(s);
+  a.E = c.E;
+  a.log2E = c.log2E;
+  a.Qt = c.Qt;
+  a.nblk = c.nblk;
+  a.fused = c.fused;
+  a.stream_nt = stream_nt_for(n * sizeof(double));
+  a.fs = s->d_fref;
+  a.fn = s->d_fref;
+  a.acc = nullptr;
+  a.out = s->d_xfer;
+  a.stage = 0;
+  e = launch_stage(s->p, a, c.lds, c.ntiles, s->stream);
+  if (e == hipSuccess) e = launch_f64_to_f32(s->d_xfer, s->g_rref, n, s->stream);
+  if (e == hipSuccess)
+    e = launch_moments(s->d_fref, s->d_vel, K, s->p, s->Q, s->pb.nx, s->pb.ny, 0, s->wall_den_inv,
+                       s->d_mref, s->d_mref + KN, s->d_mref + 2 * KN, nullptr, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "reference right-hand side");
+  return DGBGK_OK;
+}
+
+// g = 0 (graph-safe fill kernel; the region is padded to 256 bytes).
+hipError_t zero_f32(dgbgk_solver *s, float *g) {
+  const size_t n = (size_t)s->K * s->Np * s->Q;
+  return launch_fill_u64((unsigned long long *)g, (n * sizeof(float) + 7) / 8, 0ull, s->stream);
+}
+
+// Reference form: the state just written to f_ref becomes the reference,
+// with a zero correction.
+int ref_reset(dgbgk_solver *s) {
+  hipError_t e = zero_f32(s, s->g_fn);
+  if (e != hipSuccess) return hip_fail(s, e, "fill kernel");
+  return ref_refresh(s);
 }
 
 }  // namespace
@@ -547,7 +619,7 @@ int dgbgk_required_bytes(const dgbgk_problem *pb, int32_t precision, size_t *byt
   if (!bytes) return fail(nullptr, DGBGK_EINVAL, "bytes is NULL");
   int rc = validate(pb, nullptr);
   if (rc) return rc;
-  if (precision != DGBGK_FP64 && !is_fp32(precision))
+  if (!valid_precision(precision))
     return fail(nullptr, DGBGK_EINVAL, "unknown precision %d", precision);
   const int N1 = pb->p + 1;
   *bytes = make_layout((int64_t)pb->nx * pb->ny, N1 * N1, N1, pb->q, precision).total;
@@ -560,10 +632,12 @@ int dgbgk_create(const dgbgk_problem *pb, int32_t precision, void *hip_stream,
   *out = nullptr;
   int rc = validate(pb, nullptr);
   if (rc) return rc;
-  if (precision != DGBGK_FP64 && !is_fp32(precision))
+  if (!valid_precision(precision))
     return fail(nullptr, DGBGK_EINVAL, "unknown precision %d", precision);
-  if (precision == DGBGK_FP32_BF16MMA && !bf16_contraction_available(pb->p))
+  if (is_bf(precision) && !bf16_contraction_available(pb->p))
     return fail(nullptr, DGBGK_ENOTSUP, "bf16 contractions are built for p <= 4");
+  if (is_ref(precision) && !ref_form_available(pb->p, is_bf(precision)))
+    return fail(nullptr, DGBGK_ENOTSUP, "the reference form is built for p <= 4");
   if (is_fp32(precision) && (int64_t)pb->nx * pb->ny * pb->q * (pb->p + 1) * (pb->p + 1) >= ((int64_t)1 << 31))
     return fail(nullptr, DGBGK_ENOTSUP, "FP32 path: more than 2^31 degrees of freedom");
   dgbgk_solver *s = new (std::nothrow) dgbgk_solver;
@@ -632,6 +706,19 @@ int dgbgk_create(const dgbgk_problem *pb, int32_t precision, void *hip_stream,
     for (int c = 0; c < 7; ++c) s->mconst[c] += W[c] * wr;
   }
   s->lay = make_layout(s->K, s->Np, s->Nfp, s->Q, precision);
+  if (is_ref(precision)) {
+    // the reference's right-hand side runs the FP64 kernel in its own decomposition
+    s->prec = DGBGK_FP64;
+    choose_tiling(s);
+    s->ref64.fused = s->fused;
+    s->ref64.E = s->E;
+    s->ref64.log2E = s->log2E;
+    s->ref64.Qt = s->Qt;
+    s->ref64.ntiles = s->ntiles;
+    s->ref64.nblk = s->nblk;
+    s->ref64.lds = s->lds;
+    s->prec = precision;
+  }
   choose_tiling(s);
   if (is_fp32(precision) && s->lds > 160 * 1024) {
     delete s;
@@ -774,12 +861,16 @@ int dgbgk_init_equilibrium(dgbgk_solver *s, double rho0, double ux0, double uy0)
   int rc = ensure_device(s);
   if (rc) return rc;
   hipError_t e =
-      is_fp32(s->prec)
+      is_ref(s->prec)
+          ? launch_init_equilibrium(s->d_fref, s->d_vel, (int)s->K, s->Np, s->Q, rho0, ux0, uy0,
+                                    s->pb.theta, s->stream)
+      : is_fp32(s->prec)
           ? launch_init_equilibrium32(s->g_fn, s->d_vel, (int)s->K, s->Np, s->Q, rho0, ux0, uy0,
                                       s->pb.theta, s->rho_ref, s->stream)
           : launch_init_equilibrium(s->d_fn, s->d_vel, (int)s->K, s->Np, s->Q, rho0, ux0, uy0,
                                     s->pb.theta, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "init kernel");
+  if (is_ref(s->prec) && (rc = ref_reset(s))) return rc;
   s->have_state = true;
   s->steps = 0;
   return DGBGK_OK;
@@ -801,13 +892,24 @@ int dgbgk_init_moments(dgbgk_solver *s, const double *rho, const double *ux, con
   if (e == hipSuccess)
     e = hipMemcpyAsync(s->d_mom + 2 * KN, uy, KN * sizeof(double), hipMemcpyHostToDevice, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "moments copy");
-  e = is_fp32(s->prec)
+  e = is_ref(s->prec)
+          ? launch_init_moments(s->d_fref, s->d_vel, s->d_mom, (int)s->K, s->Np, s->Q, s->pb.theta,
+                                s->stream)
+      : is_fp32(s->prec)
           ? launch_init_moments32(s->g_fn, s->d_vel, s->d_mom, (int)s->K, s->Np, s->Q, s->pb.theta,
                                   s->rho_ref, s->stream)
           : launch_init_moments(s->d_fn, s->d_vel, s->d_mom, (int)s->K, s->Np, s->Q, s->pb.theta,
                                 s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // the host arrays may go away
   if (e != hipSuccess) return hip_fail(s, e, "init kernel");
+  if (is_ref(s->prec)) {
+    int rc2 = ref_reset(s);
+    if (!rc2) {
+      e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) rc2 = hip_fail(s, e, "reference set-up");
+    }
+    if (rc2) return rc2;
+  }
   s->have_state = true;
   s->steps = 0;
   return DGBGK_OK;
@@ -821,7 +923,15 @@ int dgbgk_set_state(dgbgk_solver *s, const double *f, size_t count) {
   if (rc) return rc;
   // host order f[q][k][n] into a staging buffer, then element-major into f_n
   hipError_t e;
-  if (is_fp32(s->prec)) {
+  if (is_ref(s->prec)) {
+    e = hipMemcpyAsync(s->d_xfer, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = launch_transpose(s->d_xfer, s->d_fref, (int)s->K, s->Np, s->Q, 1, s->stream);
+    if (e == hipSuccess) {
+      // the transfer buffer is reused by the reference's right-hand side
+      e = hipStreamSynchronize(s->stream);
+      if (e == hipSuccess && (rc = ref_reset(s))) return rc;
+    }
+  } else if (is_fp32(s->prec)) {
     e = hipMemcpyAsync(s->d_xfer, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
       e = launch_to_dev32(s->d_xfer, s->g_fn, s->d_vel, (int)s->K, s->Np, s->Q, s->rho_ref, s->stream);
@@ -842,7 +952,9 @@ int dgbgk_get_state(dgbgk_solver *s, double *f, size_t count) {
   if (!f || count != need) return fail(s, DGBGK_EINVAL, "state needs %zu doubles", need);
   if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
   double *stage = is_fp32(s->prec) ? s->d_xfer : s->d_b;
-  hipError_t e = is_fp32(s->prec)
+  hipError_t e = is_ref(s->prec)
+                     ? launch_from_ref(s->d_fref, s->g_fn, stage, (int)s->K, s->Np, s->Q, s->stream)
+                 : is_fp32(s->prec)
                      ? launch_from_dev32(s->g_fn, stage, s->d_vel, (int)s->K, s->Np, s->Q, s->rho_ref,
                                          s->stream)
                      : launch_transpose(s->d_fn, stage, (int)s->K, s->Np, s->Q, 0, s->stream);
@@ -974,9 +1086,15 @@ int dgbgk_rhs(dgbgk_solver *s, const double *f, double *k, size_t count) {
   if (rc) return rc;
   hipError_t e;
   if (is_fp32(s->prec)) {
+    if (is_ref(s->prec) && !s->have_state)
+      return fail(s, DGBGK_ESTATE, "the reference form evaluates L(f) as a correction to its "
+                                   "reference: call init or set_state first");
     e = hipMemcpyAsync(s->d_xfer, f, need * sizeof(double), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
-      e = launch_to_dev32(s->d_xfer, s->g_a, s->d_vel, (int)s->K, s->Np, s->Q, s->rho_ref, s->stream);
+      e = is_ref(s->prec)
+              ? launch_to_ref(s->d_xfer, s->d_fref, s->g_a, (int)s->K, s->Np, s->Q, s->stream)
+              : launch_to_dev32(s->d_xfer, s->g_a, s->d_vel, (int)s->K, s->Np, s->Q, s->rho_ref,
+                                s->stream);
     if (e != hipSuccess) return hip_fail(s, e, "rhs input copy");
     if ((rc = run_stage(s, 0, s->g_a, s->g_b, 0.0))) return rc;
     e = launch_from_dev32(s->g_b, s->d_xfer, s->d_vel, (int)s->K, s->Np, s->Q, 0.0, s->stream);
@@ -1001,6 +1119,8 @@ int dgbgk_wall_density(dgbgk_solver *s, const double *f, double *out, size_t cou
   const size_t need = (size_t)s->K * s->Np * s->Q;
   const size_t nout = (size_t)s->K * 4 * s->Nfp;
   if (!f || !out || count != need) return fail(s, DGBGK_EINVAL, "state needs %zu doubles", need);
+  if (is_ref(s->prec))
+    return fail(s, DGBGK_ENOTSUP, "the reference form forms wall densities of its correction only");
   int rc = ensure_device(s);
   if (rc) return rc;
   const bool f32 = is_fp32(s->prec);
@@ -1072,7 +1192,15 @@ int dgbgk_moments(dgbgk_solver *s, double *rho, double *ux, double *uy) {
   if (!rho || !ux || !uy) return fail(s, DGBGK_EINVAL, "NULL output");
   if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
   const size_t KN = (size_t)s->K * s->Np;
-  hipError_t e =
+  hipError_t e = hipSuccess;
+  if (is_ref(s->prec)) {  // f = f_ref + g in FP64 (transfer buffer), then the FP64 moments
+    e = launch_ref_sum(s->d_fref, s->g_fn, s->d_xfer, KN * s->Q, s->stream);
+    if (e == hipSuccess)
+      e = launch_moments(s->d_xfer, s->d_vel, (int)s->K, s->p, s->Q, s->pb.nx, s->pb.ny, 0,
+                         s->wall_den_inv, s->d_mom, s->d_mom + KN, s->d_mom + 2 * KN, nullptr,
+                         s->stream);
+  } else
+    e =
       is_fp32(s->prec)
           ? launch_moments32(s->g_fn, s->d_vel, (int)s->K, s->Np, s->Q, s->rho_ref, s->d_mom,
                              s->d_mom + KN, s->d_mom + 2 * KN, s->stream)
@@ -1088,6 +1216,15 @@ int dgbgk_moments(dgbgk_solver *s, double *rho, double *ux, double *uy) {
     if (!std::isfinite(rho[i]) || !std::isfinite(ux[i]) || !std::isfinite(uy[i]))
       return fail(s, DGBGK_ENONFINITE, "moment at node %zu is not finite", i);
   return DGBGK_OK;
+}
+
+int dgbgk_fold(dgbgk_solver *s) {
+  if (!s) return fail(nullptr, DGBGK_EINVAL, "solver is NULL");
+  if (!is_ref(s->prec)) return fail(s, DGBGK_ENOTSUP, "only the reference form has a correction to fold");
+  if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
+  hipError_t e = launch_ref_fold(s->d_fref, s->g_fn, (size_t)s->K * s->Np * s->Q, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "fold kernel");
+  return ref_refresh(s);
 }
 
 int dgbgk_synchronize(dgbgk_solver *s) {
@@ -1815,7 +1952,7 @@ int dgbgk_implicit_step_noalloc(dgbgk_solver *s, int32_t scheme, int64_t nsteps,
 
 struct dgbgk_batch {
   struct Class {
-    int prec = DGBGK_FP64, p = 1, cw = 0, contract = 0, lds_bin = 0;
+    int prec = DGBGK_FP64, p = 1, cw = 0, contract = 0, ref = 0, lds_bin = 0;
     std::vector<int> members;  // indices into s
     std::vector<int2> items;   // (member index within the class, element block)
     size_t lds = 0;
@@ -1833,9 +1970,11 @@ struct dgbgk_batch {
   std::vector<double> dt_loaded;   // dt each member's descriptors hold (NaN: none)
   std::vector<int> E_built;        // each member's elements per block when the lists were built
   std::vector<int> fused_built;    // and its fused flag
-  bool use_graph = false;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  int graph_steps = 0;                // RK4 steps per captured graph (0: eager)
+  hipGraphExec_t exec = nullptr;      // graph_steps steps
+  hipGraphExec_t exec1 = nullptr;     // one step (the remainder of a call)
+  size_t off_res = 0;                 // byte offset of the residual accumulators in dev
+  std::vector<unsigned long long> res_host;
   std::string err;
 };
 
@@ -1923,7 +2062,7 @@ int launch_class(dgbgk_batch *b, const dgbgk_batch::Class &c, int stage) {
   const int2 *items = (const int2 *)(b->dev + c.off_items);
   hipError_t e;
   if (is_fp32(c.prec))
-    e = launch_batch_stage32(c.p, stage, c.cw, c.contract, (const Stage32Args *)descs, items,
+    e = launch_batch_stage32(c.p, stage, c.cw, c.contract, c.ref, (const Stage32Args *)descs, items,
                              (int)c.items.size(), c.lds, c.groups, b->stream);
   else
     e = launch_batch_stage(c.p, stage, (const StageArgs *)descs, items, (int)c.items.size(), c.lds,
@@ -1963,10 +2102,32 @@ int enqueue_step(dgbgk_batch *b) {
 }
 
 void drop_graph(dgbgk_batch *b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->exec || b->exec1) (void)hipStreamSynchronize(b->stream);  // replays in flight
+  if (b->exec && b->exec != b->exec1) (void)hipGraphExecDestroy(b->exec);
+  if (b->exec1) (void)hipGraphExecDestroy(b->exec1);
   b->exec = nullptr;
-  b->graph = nullptr;
+  b->exec1 = nullptr;
+}
+
+// Captures `steps` RK4 steps of the batch into *out.
+int capture_batch(dgbgk_batch *b, int steps, hipGraphExec_t *out) {
+  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "begin capture: %s", hipGetErrorString(e));
+  int rc = DGBGK_OK;
+  for (int i = 0; i < steps && !rc; ++i) rc = enqueue_step(b);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(b->stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    *out = nullptr;
+    return bfail(b, DGBGK_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+  }
+  return DGBGK_OK;
 }
 
 }  // namespace
@@ -2015,14 +2176,15 @@ int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream
     if (std::find(b->solo.begin(), b->solo.end(), i) != b->solo.end()) continue;
     const bool f32 = is_fp32(s->prec);
     const int cw = f32 ? (((int64_t)s->Q * s->Np) % 4 == 0 ? 4 : 1) : 0;
-    const int contract = s->prec == DGBGK_FP32_BF16MMA;
+    const int contract = is_bf(s->prec) ? 1 : 0;
+    const int ref = is_ref(s->prec) ? 1 : 0;
     int bin = 0;
     while (bin < 3 && s->lds > bins[bin]) ++bin;
     const int prec_class = f32 ? DGBGK_FP32 : DGBGK_FP64;
     size_t k = 0;
     for (; k < b->cls.size(); ++k) {
       const auto &c = b->cls[k];
-      if (c.prec == prec_class && c.p == s->p && c.cw == cw && c.contract == contract &&
+      if (c.prec == prec_class && c.p == s->p && c.cw == cw && c.contract == contract && c.ref == ref &&
           c.lds_bin == bin)
         break;
     }
@@ -2032,6 +2194,7 @@ int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream
       c.p = s->p;
       c.cw = cw;
       c.contract = contract;
+      c.ref = ref;
       c.lds_bin = bin;
       b->cls.push_back(c);
     }
@@ -2054,10 +2217,12 @@ int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream
     const int per_cu = std::max(1, std::min(is_fp32(c.prec) ? 3 : 2, (int)((160 * 1024) / c.lds)));
     c.groups = (int)std::min<size_t>(c.items.size(), (size_t)per_cu * b->s[c.members[0]]->num_cu);
   }
+  b->off_res = off;  // one accumulator per member for the batched residuals
+  off += round_up((size_t)n * sizeof(unsigned long long));
   b->host.assign(off, 0);
   for (auto &c : b->cls)
     std::memcpy(b->host.data() + c.off_items, c.items.data(), c.items.size() * sizeof(int2));
-  hipError_t e = hipMalloc((void **)&b->dev, std::max<size_t>(off, kAlign));  // all members solo: off = 0
+  hipError_t e = hipMalloc((void **)&b->dev, off);
   if (e != hipSuccess) {
     delete b;
     return bfail(nullptr, DGBGK_ENOMEM, "hipMalloc(%zu): %s", off, hipGetErrorString(e));
@@ -2091,8 +2256,9 @@ int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream
 
 int dgbgk_batch_set_graph(dgbgk_batch *b, int32_t use_graph) {
   if (!b) return bfail(nullptr, DGBGK_EINVAL, "batch is NULL");
-  b->use_graph = use_graph != 0;
-  if (!b->use_graph) drop_graph(b);
+  if (use_graph < 0 || use_graph > 1000) return bfail(b, DGBGK_EINVAL, "use_graph must be 0..1000");
+  if (use_graph != b->graph_steps) drop_graph(b);
+  b->graph_steps = use_graph;
   return DGBGK_OK;
 }
 
@@ -2120,34 +2286,29 @@ int dgbgk_batch_step(dgbgk_batch *b, int64_t nsteps, const double *dt) {
     if (!b->solo.empty()) drop_graph(b);
   }
   if (nsteps == 0) return DGBGK_OK;
-  if (b->use_graph && !b->exec) {
-    // one eager step sets the kernels' LDS attributes before the capture
+  const int k = b->graph_steps;
+  if (k > 0 && ((nsteps >= k && !b->exec) || (nsteps % k != 0 && !b->exec1))) {
+    // one eager step first: it sets the kernels' LDS attributes outside the capture
     if ((rc = enqueue_step(b))) return rc;
     --nsteps;
     for (auto *s : b->s) ++s->steps;
-    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "begin capture: %s", hipGetErrorString(e));
-    rc = enqueue_step(b);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(b->stream, &g);
-    if (rc) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-    b->graph = g;
-    if (e != hipSuccess) {
-      drop_graph(b);
-      return bfail(b, DGBGK_EDEVICE, "graph capture: %s", hipGetErrorString(e));
-    }
+    if (!b->exec && k > 1 && (rc = capture_batch(b, k, &b->exec))) return rc;
+    if (!b->exec1 && (rc = capture_batch(b, 1, &b->exec1))) return rc;
+    if (k == 1) b->exec = b->exec1;
   }
-  for (int64_t it = 0; it < nsteps; ++it) {
-    if (b->use_graph) {
+  int64_t it = 0;
+  if (k > 0) {
+    for (; it + k <= nsteps; it += k) {
       hipError_t e = hipGraphLaunch(b->exec, b->stream);
       if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "graph launch: %s", hipGetErrorString(e));
-    } else if ((rc = enqueue_step(b))) {
-      return rc;
     }
+    for (; it < nsteps; ++it) {
+      hipError_t e = hipGraphLaunch(b->exec1, b->stream);
+      if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+    }
+  } else {
+    for (; it < nsteps; ++it)
+      if ((rc = enqueue_step(b))) return rc;
   }
   for (auto *s : b->s) s->steps += nsteps;
   return DGBGK_OK;
@@ -2157,27 +2318,41 @@ int dgbgk_batch_residuals(dgbgk_batch *b, double *r) {
   if (!b) return bfail(nullptr, DGBGK_EINVAL, "batch is NULL");
   if (!r) return bfail(b, DGBGK_EINVAL, "r is NULL");
   const size_t n = b->s.size();
-  std::vector<unsigned long long> bits(n, 0ull);
+  for (size_t i = 0; i < n; ++i) {
+    if (!b->s[i]->have_state) return bfail(b, DGBGK_ESTATE, "member %zu has no state", i);
+    if (b->s[i]->E != b->E_built[i] || b->s[i]->fused != b->fused_built[i])
+      return bfail(b, DGBGK_ESTATE, "member %zu was re-tiled after the batch was built", i);
+  }
+  // L(f) of every member (one stage-0 launch per class, the members' own
+  // kernels for large members), then one reduction launch per member into the
+  // batch's accumulators and a single copy to the host
+  unsigned long long *acc = (unsigned long long *)(b->dev + b->off_res);
+  hipError_t e = launch_fill_u64(acc, n, 0ull, b->stream);
+  if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "fill kernel: %s", hipGetErrorString(e));
+  int rc = DGBGK_OK;
+  for (const auto &c : b->cls)
+    if ((rc = launch_class(b, c, 0))) return rc;
+  for (int i : b->solo)
+    if ((rc = launch_solo(b, i, 0))) return rc;
   for (size_t i = 0; i < n; ++i) {
     dgbgk_solver *s = b->s[i];
-    if (!s->have_state) return bfail(b, DGBGK_ESTATE, "member %zu has no state", i);
-    hipStream_t saved = s->stream;
-    s->stream = b->stream;
-    int rc = residual_enqueue(s);
-    hipError_t e = hipSuccess;
-    if (!rc)
-      e = hipMemcpyAsync(&bits[i], s->d_u64, sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                         b->stream);
-    s->stream = saved;
-    if (rc) return bfail(b, rc, "member %zu: %s", i, s->err.c_str());
-    if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "residual copy: %s", hipGetErrorString(e));
+    void *fs, *out;
+    stage_buffers(s, 0, fs, out);
+    e = is_fp32(s->prec)
+            ? launch_residual32((const float *)out, s->d_vel, (int)s->K, s->Np, s->Q, s->resid_scale,
+                                acc + i, b->stream)
+            : launch_residual((const double *)out, s->d_vel, (int)s->K, s->Np, s->Q, s->resid_scale,
+                              acc + i, b->stream);
+    if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "residual kernel: %s", hipGetErrorString(e));
   }
-  hipError_t e = hipStreamSynchronize(b->stream);
-  if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "synchronize: %s", hipGetErrorString(e));
-  int rc = DGBGK_OK;
+  b->res_host.assign(n, 0ull);
+  e = hipMemcpyAsync(b->res_host.data(), acc, n * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                     b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "residual copy: %s", hipGetErrorString(e));
   for (size_t i = 0; i < n; ++i) {
     double v;
-    std::memcpy(&v, &bits[i], sizeof v);
+    std::memcpy(&v, &b->res_host[i], sizeof v);
     if (!std::isfinite(v)) {
       v = NAN;
       rc = bfail(b, DGBGK_ENONFINITE, "member %zu: residual is not finite", i);

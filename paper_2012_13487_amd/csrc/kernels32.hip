@@ -16,8 +16,20 @@
 // One work-group owns E elements and all Q velocities (the fused form of the
 // FP64 kernel): the block's tile is one contiguous run of E Q Np floats,
 // streamed with 16-byte accesses.
+//
+// Reference form (REF): the state is f = f_r + g with an FP64 reference f_r
+// (any state, refreshed from time to time by folding g into it) and the FP32
+// correction g.  Transport (volume term, upwind jumps and the wall exterior
+// state, whose density of eq. (8) is linear in the outgoing values) is linear
+// in f, so L(f_r + g) = L(f_r) + T(g) - g / tau + [f^eq(m_r + m_g) - f^eq(m_r)] / tau
+// with m the node moments; L(f_r) is computed in FP64 when the reference is
+// set and streamed in FP32, and the difference of equilibria is expanded in
+// the moment increments with FP64 node factors, so every FP32 quantity is
+// rounded relative to the correction or to the current rate, which both
+// vanish as a solve approaches its steady state.
 #include "kernels32.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -47,14 +59,15 @@ struct Lds32 {
   int part, mom, rw, nbr, vol, total;
 };
 
-__host__ __device__ inline Lds32 lds32_layout(int NP, int NFP, int S, int E, int Q, bool bf16) {
+__host__ __device__ inline Lds32 lds32_layout(int NP, int NFP, int S, int E, int Q, bool bf16,
+                                               bool ref) {
   Lds32 L;
   const int tile_d = (E * Q * S + 1) / 2;
   const int tasks = E * ((NP + 15) / 16);
   const int pairs = tasks >= 4 ? tasks : 4;
   L.part = (tile_d + 3) / 4 * 4;
-  L.mom = L.part + pairs * 7 * 16;      // float [E*NP][8] = 4 doubles per node
-  L.rw = L.mom + E * NP * 4;
+  L.mom = L.part + pairs * 7 * 16;      // float [E*NP][8] (reference form [12]) per node
+  L.rw = L.mom + E * NP * (ref ? 6 : 4);
   L.nbr = L.rw + E * 4 * NFP;
   L.vol = (L.nbr + (E * 4 + 1) / 2 + 3) / 4 * 4;
   // bf16: per wavefront a [2 NP][16] float block (Dr g and Ds g of 16
@@ -191,19 +204,29 @@ __device__ __forceinline__ void st_once32(float *p, const V &v) {
 // they do not evict the tiles neighbours still gather from (used when the
 // state arrays exceed the last-level cache); the stage output, the next
 // stage's input, is always stored normally.
-template <int P, int MODE, int CW, bool NT>
+template <int P, int MODE, int CW, bool NT, bool REF>
 __device__ __forceinline__ void update32(const Stage32Args &a, const float *tile, size_t boff, int nch,
                                          int tid, int nthr) {
   using Sh = Shape32<P>;
   constexpr int NP = Sh::NP, S = Sh::S;
-  constexpr int U = P == 4 ? 16 : 8;  // measured: p = 4 (25 nodes) 1188 -> 1150 us, p = 3 prefers 8
+  // measured: p = 4 (25 nodes) 1188 -> 1150 us, p = 3 prefers 8; the reference
+  // form's third stream (L(f_r)) keeps 8 at p = 4 (16 takes all 256 registers)
+  constexpr int U = (P == 4 && !REF) ? 16 : 8;
   using V = typename std::conditional<CW == 4, float4v, float>::type;
   const float cacc = a.c_acc, cout = a.c_out;
   const float *xr = (MODE == 1 ? a.fs : a.fn) + boff;
   float *accr = a.acc + boff;
   float *outr = a.out + boff;
+  const float *rr = REF ? a.rref + boff : nullptr;
   for (int c0 = tid; c0 < nch; c0 += nthr * U) {
-    V x[U], y[U];
+    V x[U], y[U], rv[REF ? U : 1];
+    if constexpr (REF) {  // L(f_r), added to the tile's T(g) + collision difference
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * nthr;
+        if (c < nch) rv[u] = ld_once32<NT, V>(rr + (size_t)c * CW);
+      }
+    }
     if (MODE != 0) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -226,7 +249,11 @@ __device__ __forceinline__ void update32(const Stage32Args &a, const float *tile
 #pragma unroll
       for (int i = 0; i < CW; ++i) {
         const int j = c * CW + i, r = j / NP, n = j - r * NP;
-        const float kv = tile[r * S + n];
+        float kv = tile[r * S + n];
+        if constexpr (REF) {
+          if constexpr (CW == 4) kv += rv[u][i];
+          else kv += rv[u];
+        }
         float xi = 0.0f, yi = 0.0f, ai = 0.0f, oi;
         if constexpr (CW == 4) {
           if (MODE != 0) xi = x[u][i];
@@ -255,7 +282,7 @@ __device__ __forceinline__ void update32(const Stage32Args &a, const float *tile
 // BF: the volume term's contractions Dr g, Ds g on bf16 matrix cores.
 // EFIX: elements per work-group fixed at compile time (0: a.E at run time);
 // the one-element form drops the block's index arithmetic.
-template <int P, int MODE, int CW, bool BF, int EFIX = 0>
+template <int P, int MODE, int CW, bool BF, int EFIX = 0, bool REF = false>
 __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
   using Sh = Shape32<P>;
   constexpr int N1 = Sh::N1, NP = Sh::NP, NFP = Sh::NFP, S = Sh::S, NB = Sh::NB;
@@ -263,7 +290,8 @@ __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
   using V = typename std::conditional<CW == 4, float4v, float>::type;
   extern __shared__ double lds[];
   const int E = EFIX > 0 ? EFIX : a.E, Q = a.Q;
-  const Lds32 L = lds32_layout(NP, NFP, S, E, Q, BF);
+  const Lds32 L = lds32_layout(NP, NFP, S, E, Q, BF, REF);
+  constexpr int MS = REF ? 12 : 8;  // floats per node in the moment table
   float *tile = (float *)lds;
   double *part = lds + L.part;
   float *mom = (float *)(lds + L.mom);
@@ -364,15 +392,36 @@ __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
 #pragma unroll
           for (int c = 0; c < 7; ++c) sm[c] += pp[c * 16 + col];
         }
+        float *m = mom + (e2 * NP + n2) * MS;
+        if constexpr (REF) {
+          // moments of g are the increments over the reference's (FP64)
+          const size_t KN = (size_t)a.K * NP, node = (size_t)(k0 + e2) * NP + n2;
+          const double rr = a.mref[node], urx = a.mref[KN + node], ury = a.mref[2 * KN + node];
+          const double drho = sm[0], rho = rr + drho;
+          const double ux = (rr * urx + sm[1]) / rho, uy = (rr * ury + sm[2]) / rho;
+          const double dux = ux - urx, duy = uy - ury;
+          const double h1 = a.half_theta_inv, th_inv = 2.0 * h1, h2 = h1 * th_inv;
+          // rho |u|^2 - rho_r |u_r|^2 = drho |u|^2 + rho_r (u + u_r).(u - u_r)
+          const double dq = drho * (ux * ux + uy * uy) + rr * ((ux + urx) * dux + (uy + ury) * duy);
+          m[0] = (float)(drho - dq * h1);
+          m[1] = (float)(sm[1] * th_inv);
+          m[2] = (float)(sm[2] * th_inv);
+          m[3] = (float)urx;
+          m[4] = (float)ury;
+          m[5] = (float)dux;
+          m[6] = (float)duy;
+          m[7] = (float)(drho * h2);
+          m[8] = (float)(rho * h2);
+        } else {
 #pragma unroll
-        for (int c = 0; c < 7; ++c) sm[c] += a.mconst[c];
-        const double rho = sm[0], ux = sm[1] / rho, uy = sm[2] / rho;
-        float *m = mom + (e2 * NP + n2) * 8;
-        m[0] = (float)ux;
-        m[1] = (float)uy;
-        m[2] = (float)rho;
-        m[3] = (float)(rho - a.rho_ref);
-        m[4] = (float)((ux * ux + uy * uy) * a.half_theta_inv);
+          for (int c = 0; c < 7; ++c) sm[c] += a.mconst[c];
+          const double rho = sm[0], ux = sm[1] / rho, uy = sm[2] / rho;
+          m[0] = (float)ux;
+          m[1] = (float)uy;
+          m[2] = (float)rho;
+          m[3] = (float)(rho - a.rho_ref);
+          m[4] = (float)((ux * ux + uy * uy) * a.half_theta_inv);
+        }
         if (a.wall_mask != 0) {
           const int i2 = n2 % N1, j2 = n2 / N1;
           const bool on[4] = {nbr[e2 * 4 + 0] < 0 && j2 == 0, nbr[e2 * 4 + 1] < 0 && i2 == P,
@@ -452,8 +501,10 @@ __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
           kk[i + N1 * j] = -(ax * dr + ay * ds);
         }
     }
-    // wall exterior state in deviation form, rho_w f^eq_q(1, u_b) - w_q rho_ref (FP64)
-    const double wrr = a.vel[2 * Q + q] * a.rho_ref;
+    // wall exterior state in deviation form, rho_w f^eq_q(1, u_b) - w_q rho_ref
+    // (FP64); in the reference form rho_w(g) f^eq_q(1, u_b), the wall density
+    // being that of the correction alone
+    const double wrr = REF ? 0.0 : a.vel[2 * Q + q] * a.rho_ref;
     if (cx != 0.0f) {
       const float wx = a.fsx * (-fabsf(cx));
       const double gb = a.feqb[fxc * Q + q];
@@ -480,16 +531,30 @@ __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
         for (int jj = 0; jj < N1; ++jj) kk[ii + N1 * jj] += (cy > 0.0f ? a.lift_lo[jj] : a.lift_hi[jj]) * J;
       }
     }
-    // collision: f^eq - f = w [(rho - rho_ref) + rho (e.u/theta + (e.u)^2/(2 theta^2)
-    //                          - |u|^2/(2 theta))] - g
-    const float *mm = mom + e * NP * 8;
+    const float *mm = mom + e * NP * MS;
+    if constexpr (REF) {
+      // collision difference: f^eq(m_r + m_g) - f^eq(m_r) - g, with
+      // f^eq / w = rho + e.j/theta + [rho (e.u)^2 / theta - rho |u|^2] / (2 theta):
+      // a = e.u_r, b = e.(u - u_r); rho (e.u)^2 - rho_r a^2 = drho a^2 + rho b (2a + b)
 #pragma unroll
-    for (int nn = 0; nn < NP; ++nn) {
-      const float4v m4 = *reinterpret_cast<const float4v *>(mm + 8 * nn);
-      const float usq = mm[8 * nn + 4];
-      const float eu = cx * m4[0] + cy * m4[1];
-      const float dev = wq * (m4[3] + m4[2] * (eu * (a.theta_inv + eu * a.half_theta2_inv) - usq));
-      kk[nn] += (dev - f[nn]) * a.inv_tau;
+      for (int nn = 0; nn < NP; ++nn) {
+        const float *m = mm + MS * nn;
+        const float av = cx * m[3] + cy * m[4], bv = cx * m[5] + cy * m[6];
+        const float dev =
+            wq * (m[0] + cx * m[1] + cy * m[2] + m[7] * av * av + m[8] * bv * (2.0f * av + bv));
+        kk[nn] += (dev - f[nn]) * a.inv_tau;
+      }
+    } else {
+      // collision: f^eq - f = w [(rho - rho_ref) + rho (e.u/theta + (e.u)^2/(2 theta^2)
+      //                          - |u|^2/(2 theta))] - g
+#pragma unroll
+      for (int nn = 0; nn < NP; ++nn) {
+        const float4v m4 = *reinterpret_cast<const float4v *>(mm + 8 * nn);
+        const float usq = mm[8 * nn + 4];
+        const float eu = cx * m4[0] + cy * m4[1];
+        const float dev = wq * (m4[3] + m4[2] * (eu * (a.theta_inv + eu * a.half_theta2_inv) - usq));
+        kk[nn] += (dev - f[nn]) * a.inv_tau;
+      }
     }
     float *roww = tile + r * S;
 #pragma unroll
@@ -499,14 +564,14 @@ __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
 
   // ---- 4. RK4 update, coalesced over the contiguous block -----------------------
   if (a.stream_nt)
-    update32<P, MODE, CW, true>(a, tile, boff, nch, tid, nthr);
+    update32<P, MODE, CW, true, REF>(a, tile, boff, nch, tid, nthr);
   else
-    update32<P, MODE, CW, false>(a, tile, boff, nch, tid, nthr);
+    update32<P, MODE, CW, false, REF>(a, tile, boff, nch, tid, nthr);
 }
 
-template <int P, int MODE, int CW, bool BF, int EFIX>
+template <int P, int MODE, int CW, bool BF, int EFIX, bool REF>
 __global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) {
-  stage32_block<P, MODE, CW, BF, EFIX>(
+  stage32_block<P, MODE, CW, BF, EFIX, REF>(
       a, strip_block32(xcd_block32(blockIdx.x, a.nblk), a.nx, EFIX > 0 ? EFIX : a.E, a.nblk));
 }
 
@@ -515,7 +580,7 @@ __global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) 
 // a descriptor table in the constant address space (see batch_stage_kernel).
 typedef __attribute__((address_space(4))) const Stage32Args ConstStage32Args;
 
-template <int P, int MODE, int CW, bool BF>
+template <int P, int MODE, int CW, bool BF, bool REF>
 __global__ __launch_bounds__(kBlock32) void batch_stage32_kernel(const Stage32Args *descs,
                                                                   const int2 *items, int nitems) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -530,7 +595,7 @@ __global__ __launch_bounds__(kBlock32) void batch_stage32_kernel(const Stage32Ar
 #else
     const Stage32Args a = descs[inst];  // host pass: the body is never run on the host
 #endif
-    stage32_block<P, MODE, CW, BF>(a, blk);
+    stage32_block<P, MODE, CW, BF, 0, REF>(a, blk);
     __syncthreads();  // LDS is reused by the next item
   }
 }
@@ -584,6 +649,47 @@ __global__ __launch_bounds__(256) void moments32_kernel(const float *g, const do
   if (uy) uy[i] = s2 / s0;
 }
 
+// Reference form: f_r += g, g = 0 (both element-major).
+__global__ __launch_bounds__(256) void ref_fold_kernel(double *fref, float *g, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    fref[i] += (double)g[i];
+    g[i] = 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(256) void f64_to_f32_kernel(const double *src, float *dst, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = (float)src[i];
+}
+
+__global__ __launch_bounds__(256) void ref_sum_kernel(const double *fref, const float *g, double *dst,
+                                                      size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = fref[i] + (double)g[i];
+}
+
+// host order [q][k][n] <-> element-major [k][q][n]
+__global__ void from_ref_kernel(const double *fref, const float *g, double *dst, size_t KNP, int Np,
+                                int Q) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // k * Np + n
+  const int q = blockIdx.y;
+  if (i >= KNP) return;
+  const size_t d = ((i / Np) * Q + q) * Np + i % Np;
+  dst[(size_t)q * KNP + i] = fref[d] + (double)g[d];
+}
+
+__global__ void to_ref_kernel(const double *src, const double *fref, float *g, size_t KNP, int Np,
+                              int Q) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i >= KNP) return;
+  const size_t d = ((i / Np) * Q + q) * Np + i % Np;
+  g[d] = (float)(src[(size_t)q * KNP + i] - fref[d]);
+}
+
 __device__ inline double nan_max32(double a, double b) { return (b > a || b != b) ? b : a; }
 
 __global__ __launch_bounds__(256) void residual32_kernel(const float *k, const double *vel, size_t KNP,
@@ -614,136 +720,190 @@ __global__ __launch_bounds__(256) void residual32_kernel(const float *k, const d
   }
 }
 
-template <int P, int MODE, int CW, bool BF>
+template <int P, int MODE, int CW, bool BF, bool REF>
 hipError_t launch_batch32_pmcb(const Stage32Args *descs, const int2 *items, int nitems, size_t lds,
                                int groups, hipStream_t st) {
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)batch_stage32_kernel<P, MODE, CW, BF>,
+    hipError_t e = hipFuncSetAttribute((const void *)batch_stage32_kernel<P, MODE, CW, BF, REF>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((batch_stage32_kernel<P, MODE, CW, BF>), dim3((unsigned)groups), dim3(kBlock32),
-                     lds, st, descs, items, nitems);
+  hipLaunchKernelGGL((batch_stage32_kernel<P, MODE, CW, BF, REF>), dim3((unsigned)groups),
+                     dim3(kBlock32), lds, st, descs, items, nitems);
   return hipGetLastError();
 }
 
-template <int P, int CW, bool BF>
+template <int P, int CW, bool BF, bool REF>
 hipError_t launch_batch32_pcb(int stage, const Stage32Args *descs, const int2 *items, int nitems,
                               size_t lds, int groups, hipStream_t st) {
   switch (stage) {
-    case 0: return launch_batch32_pmcb<P, 0, CW, BF>(descs, items, nitems, lds, groups, st);
-    case 1: return launch_batch32_pmcb<P, 1, CW, BF>(descs, items, nitems, lds, groups, st);
+    case 0: return launch_batch32_pmcb<P, 0, CW, BF, REF>(descs, items, nitems, lds, groups, st);
+    case 1: return launch_batch32_pmcb<P, 1, CW, BF, REF>(descs, items, nitems, lds, groups, st);
     case 2:
-    case 3: return launch_batch32_pmcb<P, 2, CW, BF>(descs, items, nitems, lds, groups, st);
-    case 4: return launch_batch32_pmcb<P, 4, CW, BF>(descs, items, nitems, lds, groups, st);
+    case 3: return launch_batch32_pmcb<P, 2, CW, BF, REF>(descs, items, nitems, lds, groups, st);
+    case 4: return launch_batch32_pmcb<P, 4, CW, BF, REF>(descs, items, nitems, lds, groups, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int P, bool BF>
+template <int P, bool BF, bool REF>
 hipError_t launch_batch32_pb(int stage, int cw, const Stage32Args *descs, const int2 *items,
                              int nitems, size_t lds, int groups, hipStream_t st) {
-  if (cw == 4) return launch_batch32_pcb<P, 4, BF>(stage, descs, items, nitems, lds, groups, st);
-  return launch_batch32_pcb<P, 1, BF>(stage, descs, items, nitems, lds, groups, st);
+  if (cw == 4) return launch_batch32_pcb<P, 4, BF, REF>(stage, descs, items, nitems, lds, groups, st);
+  return launch_batch32_pcb<P, 1, BF, REF>(stage, descs, items, nitems, lds, groups, st);
 }
 
-template <int P, int MODE, int CW, bool BF, int EFIX>
+// The reference form and the bf16 contractions are built for p <= 4.
+constexpr int kMaxRefP = 4;
+
+template <bool BF, bool REF>
+hipError_t launch_batch32_b(int p, int stage, int cw, const Stage32Args *descs, const int2 *items,
+                            int nitems, size_t lds, int groups, hipStream_t st) {
+  switch (p) {
+    case 1: return launch_batch32_pb<1, BF, REF>(stage, cw, descs, items, nitems, lds, groups, st);
+    case 2: return launch_batch32_pb<2, BF, REF>(stage, cw, descs, items, nitems, lds, groups, st);
+    case 3: return launch_batch32_pb<3, BF, REF>(stage, cw, descs, items, nitems, lds, groups, st);
+    case 4: return launch_batch32_pb<4, BF, REF>(stage, cw, descs, items, nitems, lds, groups, st);
+    default: break;
+  }
+  if constexpr (!BF && !REF) {
+    switch (p) {
+      case 5: return launch_batch32_pb<5, false, false>(stage, cw, descs, items, nitems, lds, groups, st);
+      case 6: return launch_batch32_pb<6, false, false>(stage, cw, descs, items, nitems, lds, groups, st);
+      case 7: return launch_batch32_pb<7, false, false>(stage, cw, descs, items, nitems, lds, groups, st);
+      case 8: return launch_batch32_pb<8, false, false>(stage, cw, descs, items, nitems, lds, groups, st);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P, int MODE, int CW, bool BF, int EFIX, bool REF>
 hipError_t launch32_pmcbe(const Stage32Args &a, size_t lds, hipStream_t st) {
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)stage32_kernel<P, MODE, CW, BF, EFIX>,
+    hipError_t e = hipFuncSetAttribute((const void *)stage32_kernel<P, MODE, CW, BF, EFIX, REF>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((stage32_kernel<P, MODE, CW, BF, EFIX>), dim3((unsigned)a.nblk), dim3(kBlock32),
-                     lds, st, a);
+  hipLaunchKernelGGL((stage32_kernel<P, MODE, CW, BF, EFIX, REF>), dim3((unsigned)a.nblk),
+                     dim3(kBlock32), lds, st, a);
   return hipGetLastError();
 }
 
-template <int P, int MODE, int CW, bool BF>
+template <int P, int MODE, int CW, bool BF, bool REF>
 hipError_t launch32_pmcb(const Stage32Args &a, size_t lds, hipStream_t st) {
   if constexpr (P <= 4)
-    if (a.E == 1) return launch32_pmcbe<P, MODE, CW, BF, 1>(a, lds, st);
-  return launch32_pmcbe<P, MODE, CW, BF, 0>(a, lds, st);
+    if (a.E == 1) return launch32_pmcbe<P, MODE, CW, BF, 1, REF>(a, lds, st);
+  return launch32_pmcbe<P, MODE, CW, BF, 0, REF>(a, lds, st);
 }
 
-template <int P, int MODE, bool BF>
+template <int P, int MODE, bool BF, bool REF>
 hipError_t launch32_pmb(const Stage32Args &a, size_t lds, hipStream_t st) {
-  if ((a.Q * (P + 1) * (P + 1)) % 4 == 0) return launch32_pmcb<P, MODE, 4, BF>(a, lds, st);
-  return launch32_pmcb<P, MODE, 1, BF>(a, lds, st);
+  if ((a.Q * (P + 1) * (P + 1)) % 4 == 0) return launch32_pmcb<P, MODE, 4, BF, REF>(a, lds, st);
+  return launch32_pmcb<P, MODE, 1, BF, REF>(a, lds, st);
 }
 
-template <int P, bool BF>
+template <int P, bool BF, bool REF>
 hipError_t launch32_pb(const Stage32Args &a, size_t lds, hipStream_t st) {
   switch (a.stage) {
-    case 0: return launch32_pmb<P, 0, BF>(a, lds, st);
-    case 1: return launch32_pmb<P, 1, BF>(a, lds, st);
+    case 0: return launch32_pmb<P, 0, BF, REF>(a, lds, st);
+    case 1: return launch32_pmb<P, 1, BF, REF>(a, lds, st);
     case 2:
-    case 3: return launch32_pmb<P, 2, BF>(a, lds, st);
-    case 4: return launch32_pmb<P, 4, BF>(a, lds, st);
+    case 3: return launch32_pmb<P, 2, BF, REF>(a, lds, st);
+    case 4: return launch32_pmb<P, 4, BF, REF>(a, lds, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <bool BF>
+template <bool BF, bool REF>
 hipError_t launch32_b(int p, const Stage32Args &a, size_t lds, hipStream_t st) {
   switch (p) {
-    case 1: return launch32_pb<1, BF>(a, lds, st);
-    case 2: return launch32_pb<2, BF>(a, lds, st);
-    case 3: return launch32_pb<3, BF>(a, lds, st);
-    case 4: return launch32_pb<4, BF>(a, lds, st);
-    case 5: return launch32_pb<5, BF>(a, lds, st);
-    case 6: return launch32_pb<6, BF>(a, lds, st);
-    case 7: return launch32_pb<7, BF>(a, lds, st);
-    case 8: return launch32_pb<8, BF>(a, lds, st);
-    default: return hipErrorInvalidValue;
+    case 1: return launch32_pb<1, BF, REF>(a, lds, st);
+    case 2: return launch32_pb<2, BF, REF>(a, lds, st);
+    case 3: return launch32_pb<3, BF, REF>(a, lds, st);
+    case 4: return launch32_pb<4, BF, REF>(a, lds, st);
+    default: break;
   }
+  if constexpr (!BF && !REF) {
+    switch (p) {
+      case 5: return launch32_pb<5, false, false>(a, lds, st);
+      case 6: return launch32_pb<6, false, false>(a, lds, st);
+      case 7: return launch32_pb<7, false, false>(a, lds, st);
+      case 8: return launch32_pb<8, false, false>(a, lds, st);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename K, typename... A>
+hipError_t launch_stream_kernel(K kern, size_t n, hipStream_t st, A... args) {
+  const size_t groups = std::min<size_t>((n + 255) / 256, 8192);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(256), 0, st, args..., n);
+  return hipGetLastError();
 }
 
 }  // namespace
 
-size_t stage32_lds_bytes(int p, int E, int Q, bool bf16) {
+size_t stage32_lds_bytes(int p, int E, int Q, bool bf16, bool ref) {
   const int N1 = p + 1, NP = N1 * N1;
-  return (size_t)lds32_layout(NP, N1, NP | 1, E, Q, bf16).total * sizeof(double);
+  return (size_t)lds32_layout(NP, N1, NP | 1, E, Q, bf16, ref).total * sizeof(double);
 }
 
 bool bf16_contraction_available(int p) { return p >= 1 && p <= 4; }
 
-hipError_t launch_batch_stage32(int p, int stage, int cw, int contract, const Stage32Args *descs,
-                                const int2 *items, int nitems, size_t lds, int groups,
-                                hipStream_t st) {
-  if (nitems <= 0 || groups <= 0) return hipSuccess;
-  if (contract) {
-    switch (p) {
-      case 1: return launch_batch32_pb<1, true>(stage, cw, descs, items, nitems, lds, groups, st);
-      case 2: return launch_batch32_pb<2, true>(stage, cw, descs, items, nitems, lds, groups, st);
-      case 3: return launch_batch32_pb<3, true>(stage, cw, descs, items, nitems, lds, groups, st);
-      case 4: return launch_batch32_pb<4, true>(stage, cw, descs, items, nitems, lds, groups, st);
-      default: return hipErrorInvalidValue;
-    }
-  }
-  switch (p) {
-    case 1: return launch_batch32_pb<1, false>(stage, cw, descs, items, nitems, lds, groups, st);
-    case 2: return launch_batch32_pb<2, false>(stage, cw, descs, items, nitems, lds, groups, st);
-    case 3: return launch_batch32_pb<3, false>(stage, cw, descs, items, nitems, lds, groups, st);
-    case 4: return launch_batch32_pb<4, false>(stage, cw, descs, items, nitems, lds, groups, st);
-    case 5: return launch_batch32_pb<5, false>(stage, cw, descs, items, nitems, lds, groups, st);
-    case 6: return launch_batch32_pb<6, false>(stage, cw, descs, items, nitems, lds, groups, st);
-    case 7: return launch_batch32_pb<7, false>(stage, cw, descs, items, nitems, lds, groups, st);
-    case 8: return launch_batch32_pb<8, false>(stage, cw, descs, items, nitems, lds, groups, st);
-    default: return hipErrorInvalidValue;
-  }
+bool ref_form_available(int p, int contract) {
+  (void)contract;
+  return p >= 1 && p <= kMaxRefP;
 }
 
-hipError_t launch_stage32(int p, const Stage32Args &a, size_t lds, int contract, hipStream_t st) {
-  if (!contract) return launch32_b<false>(p, a, lds, st);
-  if (!a.dmat) return hipErrorInvalidValue;
-  switch (p) {
-    case 1: return launch32_pb<1, true>(a, lds, st);
-    case 2: return launch32_pb<2, true>(a, lds, st);
-    case 3: return launch32_pb<3, true>(a, lds, st);
-    case 4: return launch32_pb<4, true>(a, lds, st);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_batch_stage32(int p, int stage, int cw, int contract, int ref,
+                                const Stage32Args *descs, const int2 *items, int nitems, size_t lds,
+                                int groups, hipStream_t st) {
+  if (nitems <= 0 || groups <= 0) return hipSuccess;
+  if (contract && ref) return launch_batch32_b<true, true>(p, stage, cw, descs, items, nitems, lds, groups, st);
+  if (contract) return launch_batch32_b<true, false>(p, stage, cw, descs, items, nitems, lds, groups, st);
+  if (ref) return launch_batch32_b<false, true>(p, stage, cw, descs, items, nitems, lds, groups, st);
+  return launch_batch32_b<false, false>(p, stage, cw, descs, items, nitems, lds, groups, st);
+}
+
+hipError_t launch_stage32(int p, const Stage32Args &a, size_t lds, int contract, int ref,
+                          hipStream_t st) {
+  if (contract && !a.dmat) return hipErrorInvalidValue;
+  if (ref && (!a.rref || !a.mref)) return hipErrorInvalidValue;
+  if (contract && ref) return launch32_b<true, true>(p, a, lds, st);
+  if (contract) return launch32_b<true, false>(p, a, lds, st);
+  if (ref) return launch32_b<false, true>(p, a, lds, st);
+  return launch32_b<false, false>(p, a, lds, st);
+}
+
+hipError_t launch_ref_fold(double *fref, float *g, size_t n, hipStream_t st) {
+  return launch_stream_kernel(ref_fold_kernel, n, st, fref, g);
+}
+
+hipError_t launch_f64_to_f32(const double *src, float *dst, size_t n, hipStream_t st) {
+  return launch_stream_kernel(f64_to_f32_kernel, n, st, src, dst);
+}
+
+hipError_t launch_ref_sum(const double *fref, const float *g, double *dst, size_t n, hipStream_t st) {
+  return launch_stream_kernel(ref_sum_kernel, n, st, fref, g, dst);
+}
+
+hipError_t launch_from_ref(const double *fref, const float *g, double *dst, int K, int Np, int Q,
+                           hipStream_t st) {
+  const size_t KNP = (size_t)K * Np;
+  dim3 grid((unsigned)((KNP + 255) / 256), (unsigned)Q);
+  hipLaunchKernelGGL(from_ref_kernel, grid, dim3(256), 0, st, fref, g, dst, KNP, Np, Q);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_ref(const double *src, const double *fref, float *g, int K, int Np, int Q,
+                         hipStream_t st) {
+  const size_t KNP = (size_t)K * Np;
+  dim3 grid((unsigned)((KNP + 255) / 256), (unsigned)Q);
+  hipLaunchKernelGGL(to_ref_kernel, grid, dim3(256), 0, st, src, fref, g, KNP, Np, Q);
+  return hipGetLastError();
 }
 
 hipError_t launch_to_dev32(const double *src, float *dst, const double *vel, int K, int Np, int Q,

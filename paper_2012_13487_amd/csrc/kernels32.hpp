@@ -23,6 +23,11 @@ struct Stage32Args {
   const double *wmom;   // [Q][16]: moment weights 1, e_x, e_y, outgoing |e.n| per side, 0...
   const uint16_t *dmat;  // [2 Np][32] bf16 rows of Dr and Ds (contraction variant only)
   double *rhow_out;     // optional [K][4][Nfp] copy of the wall densities
+  // reference form (DGBGK_FP32_REF): the state is f = f_r + g with an FP64
+  // reference f_r; rref = L(f_r) in FP32 ([k][q][n]), mref = rho, u_x, u_y of
+  // f_r per node ([3][K Np], FP64).  NULL otherwise.
+  const float *rref;
+  const double *mref;
   float D1[kMaxN1 * kMaxN1];
   float lift_lo[kMaxN1], lift_hi[kMaxN1];
   float rx, sy, fsx, fsy;
@@ -44,20 +49,37 @@ struct Stage32Args {
 // Whether the bf16 matrix-core contraction variant is built for order p.
 bool bf16_contraction_available(int p);
 
+// Whether the reference form is built for order p (and contraction variant).
+bool ref_form_available(int p, int contract);
+
 // LDS bytes of the FP32 stage kernel for (p, E, Q).
-size_t stage32_lds_bytes(int p, int E, int Q, bool bf16);
+size_t stage32_lds_bytes(int p, int E, int Q, bool bf16, bool ref);
 
 // contract: 0 FP32 vector contractions, 1 BF16 matrix-core contractions of
-// the volume term (FP32 accumulation).
-hipError_t launch_stage32(int p, const Stage32Args &a, size_t lds_bytes, int contract,
+// the volume term (FP32 accumulation).  ref: the reference form (a.rref,
+// a.mref set).
+hipError_t launch_stage32(int p, const Stage32Args &a, size_t lds_bytes, int contract, int ref,
                           hipStream_t stream);
 
 // Batched FP32 stage over problems of order p with the same access width cw
-// (4 when Q Np is a multiple of 4, else 1) and contraction variant; items and
-// descs as for launch_batch_stage.
-hipError_t launch_batch_stage32(int p, int stage, int cw, int contract, const Stage32Args *descs,
-                                const int2 *items, int nitems, size_t lds_bytes, int groups,
-                                hipStream_t stream);
+// (4 when Q Np is a multiple of 4, else 1), contraction variant and form;
+// items and descs as for launch_batch_stage.
+hipError_t launch_batch_stage32(int p, int stage, int cw, int contract, int ref,
+                                const Stage32Args *descs, const int2 *items, int nitems,
+                                size_t lds_bytes, int groups, hipStream_t stream);
+
+// Reference form helpers (element-major arrays of n = K Np Q values):
+// fold: f_r += g, g = 0;  to_f32: dst = (float) src;  sum: dst = f_r + g;
+// from_ref: dst[q][k][n] (host order) = f_r + g;  to_ref: g = src (host
+// order) - f_r.
+hipError_t launch_ref_fold(double *fref, float *g, size_t n, hipStream_t stream);
+hipError_t launch_f64_to_f32(const double *src, float *dst, size_t n, hipStream_t stream);
+hipError_t launch_ref_sum(const double *fref, const float *g, double *dst, size_t n,
+                          hipStream_t stream);
+hipError_t launch_from_ref(const double *fref, const float *g, double *dst, int K, int Np, int Q,
+                           hipStream_t stream);
+hipError_t launch_to_ref(const double *src, const double *fref, float *g, int K, int Np, int Q,
+                         hipStream_t stream);
 
 // f (double, host order f[q][k][n]) <-> g (float, element-major), with
 // g = f - offset * w_q (offset = rho_ref for states, 0 for rates).

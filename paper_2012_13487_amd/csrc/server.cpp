@@ -77,8 +77,13 @@ void drop_batch(dgbgk_server *sv) {
 
 // Admits request r at server time t: a solver at rest.  On failure the request
 // is marked failed (the server goes on with the others).
+bool ref_form(int precision) {
+  return precision == DGBGK_FP32_REF || precision == DGBGK_FP32_BF16MMA_REF;
+}
+
 bool mixed(const dgbgk_server *sv) {
-  return sv->opt.precision != DGBGK_FP64 && sv->opt.polish_below > 0.0;
+  return sv->opt.precision != DGBGK_FP64 && !ref_form(sv->opt.precision) &&
+         sv->opt.polish_below > 0.0;
 }
 
 void admit(dgbgk_server *sv, Request &r, double t) {
@@ -164,7 +169,7 @@ int dgbgk_server_create(const dgbgk_server_options *opt, void *hip_stream, dgbgk
   if (opt->hbm_budget == 0 || opt->max_active < 1 || !(opt->residual_target > 0) ||
       opt->check_every < 1 || opt->max_steps < 1 || !(opt->cfl > 0) ||
       (opt->precision != DGBGK_FP64 && opt->precision != DGBGK_FP32 &&
-       opt->precision != DGBGK_FP32_BF16MMA))
+       opt->precision != DGBGK_FP32_BF16MMA && !ref_form(opt->precision)))
     return DGBGK_EINVAL;
   dgbgk_server *sv = new (std::nothrow) dgbgk_server;
   if (!sv) return DGBGK_ENOMEM;
@@ -256,7 +261,10 @@ int dgbgk_server_run(dgbgk_server *sv, double time_limit_s) {
       std::vector<dgbgk_solver *> ss;
       for (size_t i : sv->active) ss.push_back(sv->req[i].s);
       int brc = dgbgk_batch_create(ss.data(), (int32_t)ss.size(), sv->stream, &sv->batch);
-      if (!brc && sv->opt.use_graph) brc = dgbgk_batch_set_graph(sv->batch, 1);
+      // up to 10 RK4 steps per captured graph: fewer launches per chunk, while
+      // the capture (repeated at every change of membership) stays short
+      if (!brc && sv->opt.use_graph)
+        brc = dgbgk_batch_set_graph(sv->batch, std::min(10, sv->opt.check_every));
       if (brc) {
         rc = sfail(sv, brc, "batch: %s", dgbgk_batch_last_error(sv->batch));
         break;
@@ -299,6 +307,10 @@ int dgbgk_server_run(dgbgk_server *sv, double time_limit_s) {
           any_done = true;
           if (!switch_to_fp64(sv, r)) status = DGBGK_REQ_FAILED;
         }
+      }
+      if (status == DGBGK_REQ_RUNNING && ref_form(r.prec) && dgbgk_fold(r.s) != DGBGK_OK) {
+        r.error = dgbgk_last_error(r.s);
+        status = DGBGK_REQ_FAILED;
       }
       if (status == DGBGK_REQ_RUNNING) {
         keep.push_back(sv->active[k]);

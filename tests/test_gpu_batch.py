@@ -36,10 +36,15 @@ MEMBERS = [
     (workloads.cavity(n=5, ny=3, p=3, m=10, lid=0.2), binding.FP32),
     (workloads.cavity(n=3, ny=4, p=4, m=8, lid=0.1, kn=0.6), binding.FP32),
     (workloads.cavity(n=4, ny=3, p=4, m=6, lid=0.15, kn=1.5), binding.FP32_BF16MMA),
+    # reference forms (FP64 reference + FP32 correction)
+    (workloads.cavity(n=5, ny=4, p=3, m=8, lid=0.1, kn=0.8), binding.FP32_REF),
+    (workloads.couette(nx=4, ny=5, p=2, kn=0.6), binding.FP32_BF16MMA_REF),
+    (workloads.cavity(n=3, ny=3, p=4, m=6, lid=0.2, kn=0.3), binding.FP32_REF),
 ]
 
 # bars against the FP64 oracle per precision
-TOLS = {binding.FP64: 1e-12, binding.FP32: 1e-5, binding.FP32_BF16MMA: 2e-3}
+TOLS = {binding.FP64: 1e-12, binding.FP32: 1e-5, binding.FP32_BF16MMA: 2e-3,
+        binding.FP32_REF: 1e-5, binding.FP32_BF16MMA_REF: 2e-3}
 
 
 def _make(seed_base=100):
@@ -55,7 +60,7 @@ def _dts(solvers):
     return np.array([g.stable_dt(0.2) * (1.0 + 0.01 * i) for i, g in enumerate(solvers)])
 
 
-@pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
+@pytest.mark.parametrize("graph", [0, 1, 4], ids=["eager", "graph1", "graph4"])
 def test_batch_members_match_solo(graph):
     _say(f"[gpu] batch vs solo, graph={graph}")
     members = _make()
@@ -106,7 +111,7 @@ def test_graph_replays_with_eager_work_between():
     dts = _dts(ref)
     be = binding.Batch(ref, graph=False)
     gr = _make()
-    bg = binding.Batch(gr, graph=True)
+    bg = binding.Batch(gr, graph=3)  # chunks of 3, 4, 2 and 5 steps: full graphs and remainders
     for chunk, scale in ((3, 1.0), (4, 1.0), (2, 0.5), (5, 0.5)):
         be.step(chunk, dts * scale)
         bg.step(chunk, dts * scale)

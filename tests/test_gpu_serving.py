@@ -5,7 +5,8 @@ on its own residual history); the memory budget must bound the requests on
 the device; the mixed-precision server (FP32 storage, finished in FP64) must
 reach the same target; every served result must match the FP64 oracle run
 from rest for the same number of RK4 steps (1e-12 for FP64, 1e-5 for FP32
-storage finished in FP64)."""
+storage finished in FP64 and for the reference form, which runs in FP32 to the
+end, its correction folded into its FP64 reference at every check)."""
 import sys
 
 import numpy as np
@@ -39,7 +40,7 @@ def _serve(reqs, arrivals, **kw):
     return res, mom, st
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_ref"])
 def test_served_alone_and_in_mix_identical(precision):
     _say(f"[gpu] serving {precision}: mix of {len(REQS)} vs alone")
     res, mom, st = _serve(REQS, ARRIVALS, precision=precision)
@@ -97,7 +98,7 @@ def _oracle_errors(oracle_mod, spec, steps, moments):
     return er, eu
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("fp32_ref", 1e-5)])
 def test_served_results_match_oracle(oracle_mod, precision, tol):
     """Each request of the mix, served to residual 1e-6, against the oracle
     run from rest (f = w) for exactly the request's RK4 steps at the same dt."""
