@@ -497,6 +497,9 @@ typedef struct {
   int32_t peak_active;
   size_t peak_bytes;
   int64_t precision_switches;    /* requests moved from FP32 to FP64 */
+  double dof_updates_all;        /* as dof_updates, with the steps of requests not
+                                    completed (running or stopped by a time limit) */
+  int64_t admitted;              /* requests admitted so far                     */
 } dgbgk_server_stats;
 
 int dgbgk_server_create(const dgbgk_server_options *opt, void *hip_stream, dgbgk_server **out);

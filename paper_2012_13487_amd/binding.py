@@ -58,7 +58,8 @@ class ServerStats(C.Structure):
                 ("dof_updates", C.c_double), ("latency_p50_s", C.c_double),
                 ("latency_p99_s", C.c_double), ("batch_rebuilds", C.c_int64),
                 ("chunks", C.c_int64), ("peak_active", C.c_int32), ("peak_bytes", C.c_size_t),
-                ("precision_switches", C.c_int64)]
+                ("precision_switches", C.c_int64), ("dof_updates_all", C.c_double),
+                ("admitted", C.c_int64)]
 
 
 class ImplicitOptions(C.Structure):

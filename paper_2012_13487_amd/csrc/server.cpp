@@ -361,12 +361,16 @@ int dgbgk_server_moments(const dgbgk_server *sv, int64_t id, double *rho, double
 int dgbgk_server_get_stats(const dgbgk_server *sv, dgbgk_server_stats *out) {
   if (!sv || !out) return DGBGK_EINVAL;
   std::vector<double> lat;
-  int64_t done = 0;
-  for (const Request &r : sv->req)
+  int64_t done = 0, admitted = 0;
+  double all = 0.0;
+  for (const Request &r : sv->req) {
     if (r.status >= DGBGK_REQ_CONVERGED) {
       ++done;
       lat.push_back(r.finish - r.arrival);
     }
+    if (r.status != DGBGK_REQ_WAITING) ++admitted;
+    all += (double)r.dof * 4.0 * (double)r.steps;
+  }
   out->submitted = (int64_t)sv->req.size();
   out->completed = done;
   out->wall_s = sv->wall_s;
@@ -378,6 +382,8 @@ int dgbgk_server_get_stats(const dgbgk_server *sv, dgbgk_server_stats *out) {
   out->peak_active = sv->peak_active;
   out->peak_bytes = sv->peak_bytes;
   out->precision_switches = sv->switches;
+  out->dof_updates_all = all;
+  out->admitted = admitted;
   return DGBGK_OK;
 }
 
