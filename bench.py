@@ -248,11 +248,22 @@ def serving(n_requests, dist, time_limit_s, label, precisions=("fp64", "fp32_ref
         sv = Server(hbm_budget=64 << 30, max_active=64, precision=prec, residual_target=1e-6,
                     check_every=50, max_steps=5_000_000, graph=True)
         ids = [sv.submit(r, a) for r, a in zip(reqs, arrivals)]
-        try:
-            sv.run(time_limit_s)
-        except Exception as e:  # the time limit: report what was served
-            if "time limit" not in str(e):
-                raise
+        # in slices of at most a minute (the server resumes where it stopped),
+        # reporting progress between them
+        t0 = time.perf_counter()
+        while True:
+            left = time_limit_s - (time.perf_counter() - t0)
+            try:
+                sv.run(max(1.0, min(60.0, left)))
+                break  # every request completed
+            except Exception as e:  # a time limit: report what was served
+                if "time limit" not in str(e):
+                    raise
+            st = sv.stats()
+            print(f"serving {label} {prec}: {st['completed']}/{n_requests} completed after "
+                  f"{st['wall_s']:.0f} s", file=sys.stderr, flush=True)
+            if time.perf_counter() - t0 >= time_limit_s:
+                break
         st = sv.stats()
         res = [sv.result(i) for i in ids]
         conv = sum(r["status"] == 2 for r in res)

@@ -40,7 +40,7 @@ constexpr size_t kLastLevelCacheBytes = (size_t)256 << 20;
 int stream_nt_for(size_t state_bytes) { return 4 * state_bytes > kLastLevelCacheBytes ? 1 : 0; }
 
 struct Layout {
-  size_t fn, acc, a, b, xfer, vel, feqb, wmom, dmat, mom, rhow, u64, fref, rref, mref, total;
+  size_t fn, acc, a, b, xfer, vel, feqb, wmom, dmat, mom, rhow, u64, fref, rref, mref, part, total;
 };
 
 bool is_fp32(int precision) {
@@ -75,6 +75,10 @@ Layout make_layout(int64_t K, int Np, int Nfp, int Q, int precision) {
   L.fref = off; off += ref ? round_up(ndof * sizeof(double)) : 0;
   L.rref = off; off += ref ? round_up(ndof * sizeof(float)) : 0;
   L.mref = off; off += ref ? round_up((size_t)3 * K * Np * sizeof(double)) : 0;
+  // FP64 velocity-tiled stages: moment partials of two states, up to
+  // kMaxPartialTiles tiles each (the state a stage reads, the one it writes)
+  L.part = off;
+  off += precision == DGBGK_FP64 ? 2 * round_up((size_t)kMaxPartialTiles * K * 7 * Np * sizeof(double)) : 0;
   L.total = off;
   return L;
 }
@@ -116,6 +120,10 @@ struct dgbgk_solver {
   double mconst[7] = {0, 0, 0, 0, 0, 0, 0};
   double *d_vel = nullptr, *d_feqb = nullptr, *d_wmom = nullptr, *d_mom = nullptr, *d_rhow = nullptr;
   unsigned long long *d_u64 = nullptr;
+  // velocity-tiled FP64 stages: moment partials (two slots; slot 0 holds f_n's
+  // between steps) and whether slot 0 holds those of the current f_n
+  double *d_part[2] = {nullptr, nullptr};
+  bool part_valid = false;
   // reference form: f = f_ref + g (FP64 reference, FP32 correction in the registers)
   double *d_fref = nullptr, *d_mref = nullptr;
   float *g_rref = nullptr;
@@ -136,6 +144,7 @@ struct dgbgk_solver {
   hipStream_t cap_stream = nullptr;  // capture stream (the solver's may be the null stream)
   double graph_dt = 0.0;             // dt and launch configuration the graph was captured with
   int graph_cfg[5] = {0, 0, 0, 0, 0};
+  bool graph_partials = false;       // the captured first stage reads f_n's partials
   // implicit-step workspace (allocated at the first implicit step)
   double *imp_ws = nullptr;
   size_t imp_bytes = 0;
@@ -228,6 +237,7 @@ void choose_tiling32(dgbgk_solver *s) {
 // Launch configuration: fused (all velocities of E elements per work-group)
 // when its LDS fits, else velocity tiles with a separate moments pass.
 void choose_tiling(dgbgk_solver *s) {
+  s->part_valid = false;  // the tile decomposition of any partials changes
   if (is_fp32(s->prec)) {
     choose_tiling32(s);
     return;
@@ -313,6 +323,11 @@ int ensure_device(dgbgk_solver *s) {
   s->d_mom = (double *)(b + s->lay.mom);
   s->d_rhow = (double *)(b + s->lay.rhow);
   s->d_u64 = (unsigned long long *)(b + s->lay.u64);
+  if (s->prec == DGBGK_FP64) {
+    s->d_part[0] = (double *)(b + s->lay.part);
+    s->d_part[1] = (double *)(b + s->lay.part +
+                              round_up((size_t)kMaxPartialTiles * s->K * 7 * s->Np * sizeof(double)));
+  }
   if (is_ref(s->prec)) {
     s->d_fref = (double *)(b + s->lay.fref);
     s->g_rref = (float *)(b + s->lay.rref);
@@ -487,13 +502,13 @@ int run_stage32(dgbgk_solver *s, int stage, const float *fs, float *out, double 
 // out (stage 0).  Tiled mode first reduces the moments of fs.  The state
 // pointers are FP64 arrays, or FP32 deviation arrays for the FP32 precisions.
 int run_stage(dgbgk_solver *s, int stage, const void *fs_, void *out_, double dt,
-              double *rhow_out = nullptr) {
+              double *rhow_out = nullptr, const double *pin = nullptr, double *pout = nullptr) {
   if (is_fp32(s->prec))
     return run_stage32(s, stage, (const float *)fs_, (float *)out_, dt, rhow_out);
   const double *fs = (const double *)fs_;
   double *out = (double *)out_;
   hipError_t e;
-  if (!s->fused) {
+  if (!s->fused && !pin) {
     e = launch_moments(fs, s->d_vel, (int)s->K, s->p, s->Q, s->pb.nx, s->pb.ny, s->wall_mask,
                        s->wall_den_inv, s->d_mom, s->d_mom + s->K * s->Np,
                        s->d_mom + 2 * s->K * s->Np, s->wall_mask ? s->d_rhow : nullptr, s->stream);
@@ -506,6 +521,8 @@ int run_stage(dgbgk_solver *s, int stage, const void *fs_, void *out_, double dt
   a.out = out;
   a.stage = stage;
   a.rhow_out = rhow_out;
+  a.pin = s->fused ? nullptr : pin;
+  a.pout = s->fused ? nullptr : pout;
   rk_coefficients(stage, dt, a.c_acc, a.c_out);
   if (s->persistent) {
     const int groups = (int)std::min<int64_t>(s->nblk, (int64_t)s->num_cu);
@@ -872,6 +889,7 @@ int dgbgk_init_equilibrium(dgbgk_solver *s, double rho0, double ux0, double uy0)
   if (e != hipSuccess) return hip_fail(s, e, "init kernel");
   if (is_ref(s->prec) && (rc = ref_reset(s))) return rc;
   s->have_state = true;
+  s->part_valid = false;
   s->steps = 0;
   return DGBGK_OK;
 }
@@ -911,6 +929,7 @@ int dgbgk_init_moments(dgbgk_solver *s, const double *rho, const double *ux, con
     if (rc2) return rc2;
   }
   s->have_state = true;
+  s->part_valid = false;
   s->steps = 0;
   return DGBGK_OK;
 }
@@ -942,6 +961,7 @@ int dgbgk_set_state(dgbgk_solver *s, const double *f, size_t count) {
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "set_state copy");
   s->have_state = true;
+  s->part_valid = false;
   s->steps = 0;
   return DGBGK_OK;
 }
@@ -980,9 +1000,26 @@ namespace {
 
 // One RK4 step.  Registers: f_n, acc, and two stage buffers A/B so that a
 // stage never overwrites the state its neighbours still read.
+bool uses_partials(const dgbgk_solver *s) {
+  return s->prec == DGBGK_FP64 && !s->fused && s->ntiles <= kMaxPartialTiles && s->d_part[0];
+}
+
+// Velocity-tiled FP64 stages hand the moment partials of their output to the
+// next stage (slots P0 -> P1 -> P0 -> P1 -> P0), so only the first stage
+// after f_n was set from outside a step reduces the moments in a separate pass.
 int enqueue_rk4_step(dgbgk_solver *s, double dt) {
   int rc;
   void *fn = s->d_fn, *A = s->d_a, *B = s->d_b;
+  if (uses_partials(s)) {
+    double *P0 = s->d_part[0], *P1 = s->d_part[1];
+    if ((rc = run_stage(s, 1, fn, A, dt, nullptr, s->part_valid ? P0 : nullptr, P1))) return rc;
+    s->part_valid = false;
+    if ((rc = run_stage(s, 2, A, B, dt, nullptr, P1, P0))) return rc;
+    if ((rc = run_stage(s, 3, B, A, dt, nullptr, P0, P1))) return rc;
+    if ((rc = run_stage(s, 4, A, fn, dt, nullptr, P1, P0))) return rc;
+    s->part_valid = true;
+    return DGBGK_OK;
+  }
   if ((rc = run_stage(s, 1, fn, A, dt))) return rc;
   if ((rc = run_stage(s, 2, A, B, dt))) return rc;
   if ((rc = run_stage(s, 3, B, A, dt))) return rc;
@@ -1033,6 +1070,7 @@ int capture_solver_graph(dgbgk_solver *s, double dt) {
   s->graph_dt = dt;
   const int cfg[5] = {s->fused, s->E, s->Qt, s->persistent, s->prec};
   std::memcpy(s->graph_cfg, cfg, sizeof cfg);
+  s->graph_partials = uses_partials(s);
   return DGBGK_OK;
 }
 
@@ -1058,7 +1096,8 @@ int dgbgk_step(dgbgk_solver *s, int64_t nsteps, double dt) {
   int64_t it = 0;
   if (s->graph_steps > 0 && nsteps >= s->graph_steps) {
     const int cfg[5] = {s->fused, s->E, s->Qt, s->persistent, s->prec};
-    if (!s->gexec || s->graph_dt != dt || std::memcmp(cfg, s->graph_cfg, sizeof cfg) != 0) {
+    if (!s->gexec || s->graph_dt != dt || std::memcmp(cfg, s->graph_cfg, sizeof cfg) != 0 ||
+        (s->graph_partials && !s->part_valid)) {
       // one eager step first: it sets the kernels' LDS attributes outside the capture
       if ((rc = enqueue_rk4_step(s, dt))) return rc;
       ++s->steps;
@@ -1143,7 +1182,8 @@ int dgbgk_wall_density(dgbgk_solver *s, const double *f, double *out, size_t cou
 }
 
 static int residual_enqueue(dgbgk_solver *s) {
-  int rc = run_stage(s, 0, s->d_fn, s->d_b, 0.0);
+  int rc = run_stage(s, 0, s->d_fn, s->d_b, 0.0, nullptr,
+                     uses_partials(s) && s->part_valid ? s->d_part[0] : nullptr);
   if (rc) return rc;
   hipError_t e = launch_fill_u64(s->d_u64, 1, 0ull, s->stream);
   if (e == hipSuccess)
@@ -1916,6 +1956,7 @@ int implicit_steps(dgbgk_solver *s, int32_t scheme, int64_t nsteps, double dt,
       worst = std::max(worst, fn2 / rms);
     }
     // stiffly accurate: f_{n+1} is the last stage value
+    s->part_valid = false;
     hipError_t e = launch_lincomb(n, 1.0, w.y, 0.0, nullptr, 0.0, nullptr, s->d_fn, s->stream);
     if (e != hipSuccess) return hip_fail(s, e, "lincomb");
     ++s->steps;
@@ -2081,6 +2122,7 @@ int launch_solo(dgbgk_batch *b, int i, int stage) {
   stage_buffers(s, stage, fs, out);
   hipStream_t own = s->stream;
   s->stream = b->stream;
+  if (stage != 0) s->part_valid = false;  // these stages reduce their moments in passes
   const int rc = run_stage(s, stage, fs, out, b->dt_loaded[i]);
   s->stream = own;
   if (rc) return bfail(b, rc, "member %d: %s", i, s->err.c_str());

@@ -395,10 +395,20 @@ __device__ __forceinline__ RowVel row_vel(const StageArgs &a, int qg) {
   return v;
 }
 
-template <int P>
+#ifndef DGBGK_STAGE1_ROWS
+#define DGBGK_STAGE1_ROWS 1
+#endif
+// Stage 1 of RK4 writes both of its outputs from the row phase: the
+// accumulator f_s + dt/6 k straight from registers to HBM, the stage output
+// f_s + dt/2 k into the LDS row for the coalesced store, so that the update
+// pass need not read f_s again (the tile in LDS holds L(f) by then).
+constexpr bool kStage1Rows = DGBGK_STAGE1_ROWS != 0;
+
+template <int P, bool ROW1 = false>
 __device__ __forceinline__ void row_rhs(const StageArgs &a, double *row, const double *mm,
                                         const double *rwe, const RowVel &rv, int nbx, int nby,
-                                        const double (&px)[P + 1], const double (&py)[P + 1]) {
+                                        const double (&px)[P + 1], const double (&py)[P + 1],
+                                        double *acc_row = nullptr) {
   using Sh = Shape<P>;
   constexpr int N1 = Sh::N1, NP = Sh::NP, NFP = Sh::NFP;
   const double cx = rv.cx, cy = rv.cy, wq = rv.wq;
@@ -462,6 +472,30 @@ __device__ __forceinline__ void row_rhs(const StageArgs &a, double *row, const d
     const double feq = wq * m4[2] * (m4[3] + eu * (a.theta_inv + eu * a.half_theta2_inv));
     kk[nn] += (feq - f[nn]) * a.inv_tau;
   }
+  if constexpr (ROW1) {
+    // acc = f + dt/6 k to HBM, out = f + dt/2 k to the LDS row (rk_one, MODE 1)
+    const double ca = a.c_acc, co = a.c_out;
+#pragma unroll
+    for (int nn = 0; nn < NP; ++nn) {
+      const double an = f[nn] + ca * kk[nn];
+      kk[nn] = f[nn] + co * kk[nn];
+      f[nn] = an;
+    }
+    if (Sh::VEC) {
+#pragma unroll
+      for (int c = 0; c < NP / 2; ++c) {
+        const double2v v = {f[2 * c], f[2 * c + 1]};
+        if (a.stream_nt) __builtin_nontemporal_store(v, reinterpret_cast<double2v *>(acc_row + 2 * c));
+        else *reinterpret_cast<double2v *>(acc_row + 2 * c) = v;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        if (a.stream_nt) __builtin_nontemporal_store(f[c], acc_row + c);
+        else acc_row[c] = f[c];
+      }
+    }
+  }
   if (Sh::VEC) {
 #pragma unroll
     for (int c = 0; c < NP / 2; ++c)
@@ -521,7 +555,8 @@ __device__ __forceinline__ void update_rows(const StageArgs &a, const double *ti
       go[u] = e * QNP + q * NP + CW * w;
       if (ok[u]) kv[u] = lds_get<V>(tile + (q * E + e) * S + CW * w);
     }
-    if (MODE != 0) {
+    constexpr bool LDS_OUT = MODE == 1 && kStage1Rows;  // the LDS tile holds the output
+    if (MODE != 0 && !LDS_OUT) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (ok[u]) x[u] = ld_once<NT, V>(xr + go[u]);
@@ -535,9 +570,13 @@ __device__ __forceinline__ void update_rows(const StageArgs &a, const double *ti
     for (int u = 0; u < U; ++u) {
       if (!ok[u]) continue;
       V o, an;
-      rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
+      if constexpr (LDS_OUT) {
+        o = kv[u];
+      } else {
+        rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
+      }
       *reinterpret_cast<V *>(outr + go[u]) = o;
-      if (MODE == 1 || MODE == 2) st_once<NT, V>(accr + go[u], an);
+      if (MODE == 2 || (MODE == 1 && !LDS_OUT)) st_once<NT, V>(accr + go[u], an);
     }
   }
 }
@@ -548,7 +587,7 @@ __device__ __forceinline__ void update_rows(const StageArgs &a, const double *ti
 template <int P, int MODE, bool NT>
 __device__ __forceinline__ void update_pass(const StageArgs &a, const double *tile, const double *xr,
                                             double *accr, double *outr, int c0, int Qb, int E, int Eb,
-                                            int nch, bool full, int tid, int nthr) {
+                                            int nch, bool full, int tid, int nthr, double *keep) {
   using Sh = Shape<P>;
   constexpr int NP = Sh::NP, S = Sh::S;
   constexpr int CW = Sh::VEC ? 2 : 1;
@@ -570,7 +609,8 @@ __device__ __forceinline__ void update_pass(const StageArgs &a, const double *ti
     go[u] = e * QNP + q * NP + CW * w;
     if (ok[u]) kv[u] = lds_get<V>(tile + (q * E + e) * S + CW * w);
   }
-  if (MODE != 0) {
+  constexpr bool LDS_OUT = MODE == 1 && kStage1Rows;  // the LDS tile holds the output
+  if (MODE != 0 && !LDS_OUT) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (ok[u]) x[u] = ld_once<NT, V>(xr + go[u]);
@@ -584,9 +624,19 @@ __device__ __forceinline__ void update_pass(const StageArgs &a, const double *ti
   for (int u = 0; u < U; ++u) {
     if (!ok[u]) continue;
     V o, an;
-    rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
+    if constexpr (LDS_OUT) {
+      o = kv[u];
+    } else {
+      rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
+    }
     *reinterpret_cast<V *>(outr + go[u]) = o;
-    if (MODE == 1 || MODE == 2) st_once<NT, V>(accr + go[u], an);
+    if (MODE == 2 || (MODE == 1 && !LDS_OUT)) st_once<NT, V>(accr + go[u], an);
+    if (keep && !LDS_OUT) {  // the output replaces L(f) at the same LDS position (this thread's own)
+      const int c = c0 + u * nthr;
+      int q, e, w;
+      split_access<CPE>(c, Qb, E, q, e, w);
+      lds_put(keep + (q * E + e) * S + CW * w, o);
+    }
   }
 }
 
@@ -664,6 +714,37 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
     block_moments_mfma<P, 16>(tile, part, a.wmom + (size_t)q0 * 16, E, Qb, Eb, tid, nthr);
     __syncthreads();
     block_moments_combine<P>(a, part, mom, rw, nbr, E, Eb, k0, tid);
+  } else if (a.pin) {
+    // the moments of f_s summed from the velocity tiles' partials, written by
+    // the stage that produced f_s
+    if (tid < E * NP) {
+      const int e2 = tid / NP, n2 = tid % NP;
+      if (e2 < Eb) {
+        double sm[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        const int ntl = (int)gridDim.y;
+        for (int t = 0; t < ntl; ++t) {
+          const double *pp = a.pin + (((size_t)t * a.K + k0 + e2) * 7) * NP + n2;
+#pragma unroll
+          for (int c = 0; c < 7; ++c) sm[c] += pp[c * NP];
+        }
+        const double rho = sm[0], ux = sm[1] / rho, uy = sm[2] / rho;
+        double *m = mom + (e2 * NP + n2) * 4;
+        m[0] = ux;
+        m[1] = uy;
+        m[2] = rho;
+        m[3] = 1.0 - (ux * ux + uy * uy) * a.half_theta_inv;
+        if (a.wall_mask != 0) {
+          constexpr int N1 = Sh::N1;
+          const int i2 = n2 % N1, j2 = n2 / N1;
+          const bool on[4] = {nbr[e2 * 4 + 0] < 0 && j2 == 0, nbr[e2 * 4 + 1] < 0 && i2 == P,
+                              nbr[e2 * 4 + 2] < 0 && j2 == P, nbr[e2 * 4 + 3] < 0 && i2 == 0};
+          const int fm[4] = {i2, j2, i2, j2};
+#pragma unroll
+          for (int fc = 0; fc < 4; ++fc)
+            if (on[fc]) rw[(e2 * 4 + fc) * NFP + fm[fc]] = sm[3 + fc] * a.wall_den_inv[fc];
+        }
+      }
+    }
   } else {
     if (tid < E * NP) {
       const int e2 = tid / NP, n2 = tid % NP;
@@ -695,7 +776,11 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
     const int nbx = nbr[e * 4 + (rv.cx > 0.0 ? 3 : 1)], nby = nbr[e * 4 + (rv.cy > 0.0 ? 0 : 2)];
     double px[NFP], py[NFP];
     row_traces<P>(a, qg, k0 + e, nbx, nby, px, py);
-    row_rhs<P>(a, tile + r * S, mom + e * NP * 4, rw + e * 4 * NFP, rv, nbx, nby, px, py);
+    if constexpr (MODE == 1 && kStage1Rows)
+      row_rhs<P, true>(a, tile + r * S, mom + e * NP * 4, rw + e * 4 * NFP, rv, nbx, nby, px, py,
+                       a.acc + (size_t)(k0 + e) * QNP + (size_t)qg * NP);
+    else
+      row_rhs<P>(a, tile + r * S, mom + e * NP * 4, rw + e * 4 * NFP, rv, nbx, nby, px, py);
   }
   __syncthreads();
 
@@ -704,8 +789,34 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
     const double *xr = (MODE == 1 ? a.fs : MODE == 2 ? a.fn : a.acc) + boff;
     double *accr = a.acc + boff;
     double *outr = a.out + boff;
+    double *keep = (MODE != 0 && a.pout) ? tile : nullptr;
     for (int c0 = tid; c0 < nch; c0 += nthr * U)
-      update_pass<P, MODE, NTM == 1>(a, tile, xr, accr, outr, c0, Qb, E, Eb, nch, full, tid, nthr);
+      update_pass<P, MODE, NTM == 1>(a, tile, xr, accr, outr, c0, Qb, E, Eb, nch, full, tid, nthr,
+                                     keep);
+    if (keep) {
+      // moment partials of the stage output over this velocity tile, for the
+      // next stage (its output values replaced L(f) in the LDS tile)
+      __syncthreads();
+      block_moments_mfma<P, 16>(tile, part, a.wmom + (size_t)q0 * 16, E, Qb, Eb, tid, nthr);
+      __syncthreads();
+      const int ks = moment_slices(P, E);
+      constexpr int NB = (NP + 15) / 16;
+      if (tid < E * NP) {
+        const int e2 = tid / NP, n2 = tid % NP;
+        if (e2 < Eb) {
+          const int t = e2 * NB + n2 / 16, col = n2 % 16;
+          double sm[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+          for (int sl = 0; sl < ks; ++sl) {
+            const double *pp = part + ((size_t)(t * ks + sl) * 7) * 16;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) sm[c] += pp[c * 16 + col];
+          }
+          double *po = a.pout + (((size_t)tile_y * a.K + k0 + e2) * 7) * NP + n2;
+#pragma unroll
+          for (int c = 0; c < 7; ++c) po[c * NP] = sm[c];
+        }
+      }
+    }
   } else if (a.stream_nt) {
     update_rows<P, MODE, true>(a, tile, boff, Qb, E, Eb, nch, full, tid, nthr);
   } else {

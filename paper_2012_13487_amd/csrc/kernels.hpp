@@ -28,6 +28,12 @@ struct StageArgs {
   const double *rhow;  // [K][4][Nfp]: diffuse-wall densities (tiled mode only)
   const double *wmom;  // [Q][16]: moment weights 1, e_x, e_y, outgoing |e.n| per side, 0...
   double *rhow_out;    // optional [K][4][Nfp] copy of the wall densities (fused mode)
+  // velocity-tiled mode: moment partials [tile][K][7][Np] (rho, rho u_x, rho u_y
+  // and the outgoing wall fluxes summed over each velocity tile).  pin: those
+  // of fs, read instead of mom / rhow (NULL: use mom / rhow); pout: those of
+  // out, written by stages 1..4 (NULL: none).
+  const double *pin;
+  double *pout;
   double D1[kMaxN1 * kMaxN1];  // 1-D GLL differentiation matrix
   double lift_lo[kMaxN1];      // M1^{-1} e_0: lift of a flux on the left / bottom face
   double lift_hi[kMaxN1];      // M1^{-1} e_p: lift of a flux on the right / top face
@@ -49,6 +55,9 @@ struct StageArgs {
   int fused;                   // 1: moments and wall densities computed in-block
   int stream_nt;               // 1: x and the accumulator move with non-temporal hints
 };
+
+// Velocity tiles for which the tiled stage kernels exchange moment partials.
+constexpr int kMaxPartialTiles = 4;
 
 // LDS bytes of the stage kernel for (p, E, Qt).
 size_t stage_lds_bytes(int p, int E, int Qt);

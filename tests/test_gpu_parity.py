@@ -151,8 +151,12 @@ def test_fused_high_order_steps_match_oracle(oracle_mod, name, spec, tiling):
     assert _rel(g.get_state(), o.get_state()) < TOL
 
 
-@pytest.mark.parametrize("tiling", [None, (2, 13), (4, 0)])
+@pytest.mark.parametrize("tiling", [None, (2, 13), (4, 0), (2, 50), (2, 34), (2, 25)],
+                         ids=["fused", "tiles8", "persistent", "tiles2", "tiles3_ragged", "tiles4"])
 def test_cavity_perturbed_steps_match_oracle(oracle_mod, tiling):
+    """40 steps in each decomposition; with 2 to 4 velocity tiles the stages
+    hand their moment partials on (no moments pass after the first stage),
+    and the residual then reads f_n's partials too."""
     _say(f"[gpu] cavity 10x7 p3 nc10 perturbed, tiling={tiling}")
     spec = workloads.cavity(n=10, ny=7, p=3, m=10, lid=0.1, kn=0.5)
     g, o = _pair(oracle_mod, spec, tiling)
@@ -160,18 +164,26 @@ def test_cavity_perturbed_steps_match_oracle(oracle_mod, tiling):
     g.set_state(f)
     o.set_state(f)
     dt = o.stable_dt(0.2)
-    g.step(40, dt)
-    o.rk4(40, dt)
+    g.step(15, dt)
+    o.rk4(15, dt)
+    r, rc = o.residual()
+    assert rc == 0 and abs(g.residual() - r) < TOL * r
+    g.step(25, dt)
+    o.rk4(25, dt)
     er, eu = _moment_errors(g, o)
     assert er < TOL and eu < TOL, (er, eu)
     assert _rel(g.get_state(), o.get_state()) < TOL
+    r, rc = o.residual()
+    assert rc == 0 and abs(g.residual() - r) < TOL * r
 
 
 @pytest.mark.parametrize("name,spec,tiling", [
     ("couette_8x8_p2_gh4", workloads.COUETTE_8x8_P2_D2Q16, None),
     ("cavity_5x3_p4_nc6_tiled", workloads.cavity(n=5, ny=3, p=4, m=6, lid=0.2), (2, 7)),
-    ("cavity_9x7_p3_nc9_persistent", workloads.cavity(n=9, ny=7, p=3, m=9, lid=0.15), (4, 0))],
-    ids=["couette_8x8_p2_gh4", "cavity_5x3_p4_nc6_tiled", "cavity_9x7_p3_nc9_persistent"])
+    ("cavity_9x7_p3_nc9_persistent", workloads.cavity(n=9, ny=7, p=3, m=9, lid=0.15), (4, 0)),
+    ("cavity_6x5_p3_nc10_tiles3", workloads.cavity(n=6, ny=5, p=3, m=10, lid=0.1), (2, 34))],
+    ids=["couette_8x8_p2_gh4", "cavity_5x3_p4_nc6_tiled", "cavity_9x7_p3_nc9_persistent",
+         "cavity_6x5_p3_nc10_tiles3"])
 def test_graph_replayed_steps_identical_to_eager(oracle_mod, name, spec, tiling):
     """dgbgk_set_graph: steps replayed from a captured hipGraph, with step counts
     that are not multiples of the graph length, a change of dt (re-capture) and
