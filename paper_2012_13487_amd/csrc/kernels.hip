@@ -398,10 +398,14 @@ __device__ __forceinline__ RowVel row_vel(const StageArgs &a, int qg) {
 #ifndef DGBGK_STAGE1_ROWS
 #define DGBGK_STAGE1_ROWS 1
 #endif
-// Stage 1 of RK4 writes both of its outputs from the row phase: the
-// accumulator f_s + dt/6 k straight from registers to HBM, the stage output
-// f_s + dt/2 k into the LDS row for the coalesced store, so that the update
-// pass need not read f_s again (the tile in LDS holds L(f) by then).
+// Stage 1 of RK4 in velocity-tiled blocks writes both of its outputs from the
+// row phase: the accumulator f_s + dt/6 k straight from registers to HBM, the
+// stage output f_s + dt/2 k into the LDS row for the coalesced store, so that
+// the update pass need not read f_s again (the tile in LDS holds L(f) by
+// then).  Measured: 2633 -> 2577 us per stage on the 128x128 p = 4 NC 24x24
+// cavity; the fused one-element blocks of the 64x64 p = 3 cavity are faster
+// without it (104 against 112 us: the row-wise stores of the accumulator
+// scatter over 128-byte lines).
 constexpr bool kStage1Rows = DGBGK_STAGE1_ROWS != 0;
 
 template <int P, bool ROW1 = false>
@@ -555,7 +559,7 @@ __device__ __forceinline__ void update_rows(const StageArgs &a, const double *ti
       go[u] = e * QNP + q * NP + CW * w;
       if (ok[u]) kv[u] = lds_get<V>(tile + (q * E + e) * S + CW * w);
     }
-    constexpr bool LDS_OUT = MODE == 1 && kStage1Rows;  // the LDS tile holds the output
+    constexpr bool LDS_OUT = false;  // fused blocks: the update pass reads f_s again
     if (MODE != 0 && !LDS_OUT) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
@@ -776,7 +780,7 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
     const int nbx = nbr[e * 4 + (rv.cx > 0.0 ? 3 : 1)], nby = nbr[e * 4 + (rv.cy > 0.0 ? 0 : 2)];
     double px[NFP], py[NFP];
     row_traces<P>(a, qg, k0 + e, nbx, nby, px, py);
-    if constexpr (MODE == 1 && kStage1Rows)
+    if constexpr (MODE == 1 && kStage1Rows && !FUSED)
       row_rhs<P, true>(a, tile + r * S, mom + e * NP * 4, rw + e * 4 * NFP, rv, nbx, nby, px, py,
                        a.acc + (size_t)(k0 + e) * QNP + (size_t)qg * NP);
     else
