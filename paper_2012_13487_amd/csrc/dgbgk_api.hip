@@ -90,6 +90,10 @@ thread_local std::string g_create_error;
 // launch: 2^22 DOF fill the GPU with 1024 or more work-groups.
 constexpr int64_t kSoloDof = (int64_t)1 << 22;
 
+// Streams a batch spreads its independent chains over (the hardware queues
+// a process gets by default).
+constexpr size_t kBatchLanes = 4;
+
 }  // namespace
 
 struct dgbgk_solver {
@@ -2011,6 +2015,13 @@ struct dgbgk_batch {
   std::vector<double> dt_loaded;   // dt each member's descriptors hold (NaN: none)
   std::vector<int> E_built;        // each member's elements per block when the lists were built
   std::vector<int> fused_built;    // and its fused flag
+  // independent chains (a class, or a large member) are spread over up to
+  // kBatchLanes streams forked from and joined to `stream` around each call
+  // (or captured graph), so that small kernels run beside large ones
+  std::vector<hipStream_t> lanes;
+  std::vector<hipEvent_t> lane_done;
+  hipEvent_t fork = nullptr;
+  std::vector<int> class_lane, solo_lane;
   int graph_steps = 0;                // RK4 steps per captured graph (0: eager)
   hipGraphExec_t exec = nullptr;      // graph_steps steps
   hipGraphExec_t exec1 = nullptr;     // one step (the remainder of a call)
@@ -2097,17 +2108,17 @@ int upload_descriptors(dgbgk_batch *b) {
   return DGBGK_OK;
 }
 
-int launch_class(dgbgk_batch *b, const dgbgk_batch::Class &c, int stage) {
+int launch_class(dgbgk_batch *b, const dgbgk_batch::Class &c, int stage, hipStream_t st) {
   const size_t nm = c.members.size();
   const void *descs = b->dev + c.off_desc + (size_t)stage * nm * c.desc_size;
   const int2 *items = (const int2 *)(b->dev + c.off_items);
   hipError_t e;
   if (is_fp32(c.prec))
     e = launch_batch_stage32(c.p, stage, c.cw, c.contract, c.ref, (const Stage32Args *)descs, items,
-                             (int)c.items.size(), c.lds, c.groups, b->stream);
+                             (int)c.items.size(), c.lds, c.groups, st);
   else
     e = launch_batch_stage(c.p, stage, (const StageArgs *)descs, items, (int)c.items.size(), c.lds,
-                           c.groups, b->stream);
+                           c.groups, st);
   if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "batched stage kernel: %s", hipGetErrorString(e));
   return DGBGK_OK;
 }
@@ -2116,12 +2127,12 @@ int launch_class(dgbgk_batch *b, const dgbgk_batch::Class &c, int stage) {
 // its single-problem stage kernels, in its own decomposition (same results as
 // stepping it alone), and packs only the smaller members into the persistent
 // kernels, which pay off where launches dominate.
-int launch_solo(dgbgk_batch *b, int i, int stage) {
+int launch_solo(dgbgk_batch *b, int i, int stage, hipStream_t st) {
   dgbgk_solver *s = b->s[i];
   void *fs, *out;
   stage_buffers(s, stage, fs, out);
   hipStream_t own = s->stream;
-  s->stream = b->stream;
+  s->stream = st;
   if (stage != 0) s->part_valid = false;  // these stages reduce their moments in passes
   const int rc = run_stage(s, stage, fs, out, b->dt_loaded[i]);
   s->stream = own;
@@ -2129,19 +2140,36 @@ int launch_solo(dgbgk_batch *b, int i, int stage) {
   return DGBGK_OK;
 }
 
-int enqueue_step(dgbgk_batch *b) {
-  for (int stage = 1; stage <= 4; ++stage) {
-    for (const auto &c : b->cls) {
-      int rc = launch_class(b, c, stage);
-      if (rc) return rc;
-    }
-    for (int i : b->solo) {
-      int rc = launch_solo(b, i, stage);
-      if (rc) return rc;
-    }
+// nsteps RK4 steps of every chain; with lanes, each chain on its own lane
+// stream between a fork from and a join to the batch's stream.
+int enqueue_steps(dgbgk_batch *b, int64_t nsteps) {
+  const bool multi = !b->lanes.empty();
+  hipError_t e = hipSuccess;
+  if (multi) {
+    e = hipEventRecord(b->fork, b->stream);
+    for (size_t k = 0; k < b->lanes.size() && e == hipSuccess; ++k)
+      e = hipStreamWaitEvent(b->lanes[k], b->fork, 0);
+    if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "lane fork: %s", hipGetErrorString(e));
   }
-  return DGBGK_OK;
+  int rc = DGBGK_OK;
+  for (int64_t it = 0; it < nsteps && !rc; ++it)
+    for (int stage = 1; stage <= 4 && !rc; ++stage) {
+      for (size_t c = 0; c < b->cls.size() && !rc; ++c)
+        rc = launch_class(b, b->cls[c], stage, multi ? b->lanes[b->class_lane[c]] : b->stream);
+      for (size_t j = 0; j < b->solo.size() && !rc; ++j)
+        rc = launch_solo(b, b->solo[j], stage, multi ? b->lanes[b->solo_lane[j]] : b->stream);
+    }
+  if (multi) {  // join (also after a failed launch, so that a capture can end)
+    for (size_t k = 0; k < b->lanes.size() && e == hipSuccess; ++k) {
+      e = hipEventRecord(b->lane_done[k], b->lanes[k]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->lane_done[k], 0);
+    }
+    if (e != hipSuccess && !rc) rc = bfail(b, DGBGK_EDEVICE, "lane join: %s", hipGetErrorString(e));
+  }
+  return rc;
 }
+
+int enqueue_step(dgbgk_batch *b) { return enqueue_steps(b, 1); }
 
 void drop_graph(dgbgk_batch *b) {
   if (b->exec || b->exec1) (void)hipStreamSynchronize(b->stream);  // replays in flight
@@ -2155,8 +2183,7 @@ void drop_graph(dgbgk_batch *b) {
 int capture_batch(dgbgk_batch *b, int steps, hipGraphExec_t *out) {
   hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "begin capture: %s", hipGetErrorString(e));
-  int rc = DGBGK_OK;
-  for (int i = 0; i < steps && !rc; ++i) rc = enqueue_step(b);
+  int rc = enqueue_steps(b, steps);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(b->stream, &g);
   if (rc) {
@@ -2279,6 +2306,46 @@ int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream
     }
     b->own_stream = true;
   }
+  // lanes: chains balanced by DOF, largest first onto the least loaded lane
+  {
+    struct Chain { int64_t dof; int cls; int solo; };
+    std::vector<Chain> ch;
+    for (size_t c = 0; c < b->cls.size(); ++c) {
+      int64_t d = 0;
+      for (int m : b->cls[c].members) d += b->s[m]->K * b->s[m]->Np * b->s[m]->Q;
+      ch.push_back({d, (int)c, -1});
+    }
+    for (size_t j = 0; j < b->solo.size(); ++j) {
+      const dgbgk_solver *m = b->s[b->solo[j]];
+      ch.push_back({m->K * m->Np * m->Q, -1, (int)j});
+    }
+    const int nl = (int)std::min<size_t>(ch.size(), kBatchLanes);
+    if (nl >= 2) {
+      std::sort(ch.begin(), ch.end(), [](const Chain &x, const Chain &y) { return x.dof > y.dof; });
+      std::vector<int64_t> load(nl, 0);
+      b->class_lane.assign(b->cls.size(), 0);
+      b->solo_lane.assign(b->solo.size(), 0);
+      for (const Chain &c : ch) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[k] += c.dof;
+        if (c.cls >= 0) b->class_lane[c.cls] = k;
+        else b->solo_lane[c.solo] = k;
+      }
+      e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+      for (int k = 0; k < nl && e == hipSuccess; ++k) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) b->lanes.push_back(st);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) b->lane_done.push_back(ev);
+      }
+      if (e != hipSuccess) {
+        dgbgk_batch_destroy(b);
+        return bfail(nullptr, DGBGK_EDEVICE, "lane streams: %s", hipGetErrorString(e));
+      }
+    }
+  }
   b->dt_loaded.assign(n, std::nan(""));
   b->E_built.resize(n);
   b->fused_built.resize(n);
@@ -2348,9 +2415,8 @@ int dgbgk_batch_step(dgbgk_batch *b, int64_t nsteps, const double *dt) {
       hipError_t e = hipGraphLaunch(b->exec1, b->stream);
       if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "graph launch: %s", hipGetErrorString(e));
     }
-  } else {
-    for (; it < nsteps; ++it)
-      if ((rc = enqueue_step(b))) return rc;
+  } else if ((rc = enqueue_steps(b, nsteps - it))) {
+    return rc;
   }
   for (auto *s : b->s) s->steps += nsteps;
   return DGBGK_OK;
@@ -2373,9 +2439,9 @@ int dgbgk_batch_residuals(dgbgk_batch *b, double *r) {
   if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "fill kernel: %s", hipGetErrorString(e));
   int rc = DGBGK_OK;
   for (const auto &c : b->cls)
-    if ((rc = launch_class(b, c, 0))) return rc;
+    if ((rc = launch_class(b, c, 0, b->stream))) return rc;
   for (int i : b->solo)
-    if ((rc = launch_solo(b, i, 0))) return rc;
+    if ((rc = launch_solo(b, i, 0, b->stream))) return rc;
   for (size_t i = 0; i < n; ++i) {
     dgbgk_solver *s = b->s[i];
     void *fs, *out;
@@ -2421,6 +2487,12 @@ void dgbgk_batch_destroy(dgbgk_batch *b) {
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   drop_graph(b);
   if (b->dev) (void)hipFree(b->dev);
+  for (hipStream_t st : b->lanes) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  for (hipEvent_t ev : b->lane_done) (void)hipEventDestroy(ev);
+  if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
