@@ -457,6 +457,8 @@ def main():
                          "report steps and time")
     ap.add_argument("--converge-max-s", type=float, default=1000.0)
     ap.add_argument("--no-couette", action="store_true")
+    ap.add_argument("--precision-steps", default="100,20", metavar="S,B",
+                    help="RK4 steps timed on the 64x64 and on the 128x128 precision workloads")
     ap.add_argument("--serving-full", type=int, default=0, metavar="N",
                     help="only serve N requests of the full-size mixed distribution (both "
                          "precisions, each under --serving-time-limit seconds)")
@@ -586,7 +588,8 @@ def main():
     if not args.no_couette:
         out["couette_config1"] = couette_config1()
     if not args.no_precision_path:
-        out["precision_path"] = precision_path(100, 20)
+        ps, pb = (int(x) for x in args.precision_steps.split(","))
+        out["precision_path"] = precision_path(ps, pb)
     if not args.no_batching:
         out["batching"] = batching(10)
     if not args.no_serving:
