@@ -210,8 +210,10 @@ __device__ __forceinline__ void update32(const Stage32Args &a, const float *tile
   using Sh = Shape32<P>;
   constexpr int NP = Sh::NP, S = Sh::S;
   // measured: p = 4 (25 nodes) 1188 -> 1150 us, p = 3 prefers 8; the reference
-  // form's third stream (L(f_r)) keeps 8 at p = 4 (16 takes all 256 registers)
-  constexpr int U = (P == 4 && !REF) ? 16 : 8;
+  // form's third stream (L(f_r)) takes registers: 8 at p = 4 (16 takes all 256;
+  // 4 measured 1332 against 1319 us), 4 below (p = 3: 79.6 against 92.1 us with 8,
+  // three work-groups per CU instead of two)
+  constexpr int U = REF ? (P == 4 ? 8 : 4) : (P == 4 ? 16 : 8);
   using V = typename std::conditional<CW == 4, float4v, float>::type;
   const float cacc = a.c_acc, cout = a.c_out;
   const float *xr = (MODE == 1 ? a.fs : a.fn) + boff;
@@ -312,6 +314,20 @@ __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
     nbr[tid] = e < Eb ? neighbour32(k0 + e, fc, a) : -1;
   }
 
+  // reference form: the reference moments of this thread's node are loaded
+  // before the tile (they arrive first; loads complete in order) and used in
+  // phase 2, instead of a dependent load after the moment product
+  const bool mref_pre = REF && E * NP <= nthr;
+  double pre_rr = 0.0, pre_ux = 0.0, pre_uy = 0.0;
+  if constexpr (REF) {
+    if (mref_pre && tid < Eb * NP) {
+      const size_t KN = (size_t)a.K * NP, node = (size_t)k0 * NP + tid;
+      pre_rr = a.mref[node];
+      pre_ux = a.mref[KN + node];
+      pre_uy = a.mref[2 * KN + node];
+    }
+  }
+
   // ---- 1. the block's tile into LDS: row r = e Q + q, node n at r S + n --------
   for (int c0 = tid; c0 < nch; c0 += nthr * U) {
     V v[U];
@@ -396,7 +412,9 @@ __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
         if constexpr (REF) {
           // moments of g are the increments over the reference's (FP64)
           const size_t KN = (size_t)a.K * NP, node = (size_t)(k0 + e2) * NP + n2;
-          const double rr = a.mref[node], urx = a.mref[KN + node], ury = a.mref[2 * KN + node];
+          const double rr = mref_pre ? pre_rr : a.mref[node];
+          const double urx = mref_pre ? pre_ux : a.mref[KN + node];
+          const double ury = mref_pre ? pre_uy : a.mref[2 * KN + node];
           const double drho = sm[0], rho = rr + drho;
           const double ux = (rr * urx + sm[1]) / rho, uy = (rr * ury + sm[2]) / rho;
           const double dux = ux - urx, duy = uy - ury;
