@@ -36,6 +36,8 @@ ALG_BYTES_PER_DOF_STAGE = 32.0  # FP64 RK4, 3 registers: 24/40/40/24 B per stage
 # kernels move); the method's own FP32 figure (3 registers) is 16 B
 ALG_BYTES_PER_DOF_STAGE_FP32 = 17.0
 ALG_BYTES_PER_DOF_STAGE_FP32_METHOD = 16.0
+# reference form: the FP32 increment form plus the FP32 L(f_r) read once per stage
+ALG_BYTES_PER_DOF_STAGE_REF = 21.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_cavity64x64_p3_nc16_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2012_13487_amd", "csrc", "kernels.hip")
 
@@ -122,9 +124,9 @@ def precision_path(steps_small, steps_big):
     out = {}
     for key, spec, steps, precs in (
             ("cavity64x64_p3_nc16", workloads.CAVITY_64x64_P3_NC16, steps_small,
-             ("fp32", "fp32_bf16mma")),
+             ("fp32", "fp32_bf16mma", "fp32_ref")),
             ("cavity128x128_p4_nc24_kn8", workloads.CAVITY_128x128_P4_NC24_KN8, steps_big,
-             ("fp32", "fp32_bf16mma", "fp64"))):
+             ("fp32", "fp32_bf16mma", "fp32_ref", "fp64"))):
         entry = {}
         for prec in precs:
             g = Solver.from_spec(spec, precision=prec, stream="torch", torch_memory=True)
@@ -133,14 +135,15 @@ def precision_path(steps_small, steps_big):
             time_steps(g, 2, dt)
             ms = time_steps(g, steps, dt)
             stage_us = 1000.0 * ms / (4 * steps)
-            bpd = ALG_BYTES_PER_DOF_STAGE if prec == "fp64" else ALG_BYTES_PER_DOF_STAGE_FP32
+            bpd = (ALG_BYTES_PER_DOF_STAGE if prec == "fp64" else
+                   ALG_BYTES_PER_DOF_STAGE_REF if prec == "fp32_ref" else ALG_BYTES_PER_DOF_STAGE_FP32)
             ach = bpd * g.ndof / (stage_us * 1e-6) / 1e9
             entry["dof"] = g.ndof
             entry[prec] = {"value": g.ndof * 4 * steps / (ms / 1000.0), "unit": "DOF-updates/s",
                            "avg_launch_us": stage_us, "alg_bytes_per_dof_stage": bpd,
                            "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS, "steps": steps,
                            "tiling": g.tiling()}
-            if prec != "fp64":
+            if prec in ("fp32", "fp32_bf16mma"):
                 # the method's 3-register FP32 figure, beside the increment form's
                 m = ALG_BYTES_PER_DOF_STAGE_FP32_METHOD * g.ndof / (stage_us * 1e-6) / 1e9
                 entry[prec]["frac_at_16B_per_dof_stage"] = m / HBM_PEAK_GBS
@@ -149,10 +152,12 @@ def precision_path(steps_small, steps_big):
     big = out["cavity128x128_p4_nc24_kn8"]
     out["fp32_over_fp64_precision_workload"] = big["fp32"]["value"] / big["fp64"]["value"]
     out["bf16_over_fp64_precision_workload"] = big["fp32_bf16mma"]["value"] / big["fp64"]["value"]
+    out["ref_over_fp64_precision_workload"] = big["fp32_ref"]["value"] / big["fp64"]["value"]
     out["note"] = ("fp32 = state stored as the FP32 deviation from w_q; moments, wall densities and "
                    "residual in FP64 (error vs the FP64 oracle <= 1e-5 in the GPU tests); "
                    "fp32_bf16mma = the same with the volume contractions on bf16 matrix cores "
-                   "(<= 2e-3)")
+                   "(<= 2e-3); fp32_ref = FP32 correction to an FP64 reference state, L(f_r) "
+                   "streamed in FP32 (<= 1e-5, reaches FP64's steady-state residuals)")
     return out
 
 
@@ -362,9 +367,10 @@ def implicit_path(steps=2, mult=10.0, race_target=1e-6):
 
 def couette_config1(repeats=5):
     """The plain-method Couette workload (8x8 quads, p=2, D2Q16, Kn=1, 200 RK4
-    steps from rest, 9,216 DOF): launch-bound, so timed with ordinary launches
-    and with the steps replayed from a captured hipGraph (50 steps per graph),
-    each the median of `repeats` 200-step solves."""
+    steps from rest, 9,216 DOF): latency-bound, so timed with the autotuned
+    block size, with ordinary launches and with the steps replayed from a
+    captured hipGraph (50 steps per graph), each the median of `repeats`
+    200-step solves."""
     import workloads
     from paper_2012_13487_amd import Solver
 
@@ -377,6 +383,9 @@ def couette_config1(repeats=5):
         g.set_graph(k)
         dt = g.stable_dt(spec.cfl)
         g.init_equilibrium()
+        # the autotuner's block size: alone, this 64-element problem runs fastest with
+        # one element per work-group (the automatic choice, 16, suits batches of it)
+        g.autotune(20)
         g.step(spec.steps, dt)  # warm-up (and the graph capture)
         times = []
         for _ in range(repeats):

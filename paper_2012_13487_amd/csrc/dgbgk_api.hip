@@ -219,16 +219,11 @@ int validate(const dgbgk_problem *pb, dgbgk_solver *s) {
 // strips (126 vs 129 us FP64, 68.5 vs 69.5 us FP32).
 constexpr int64_t kMaxBlockDof = 4096;
 
-// Blocks the automatic choice keeps, where the mesh allows: two per CU.  A
-// small problem (the 8x8 p = 2 Couette workload: 64 elements) then runs one
-// element per work-group on 64 CUs rather than 16 elements on 4.
-constexpr int64_t kMinBlocks = 512;
-
 void choose_tiling32(dgbgk_solver *s) {
   const int NP = s->Np;
   const bool bf = is_bf(s->prec), ref = is_ref(s->prec);
   int E = 1;
-  while ((int64_t)E * 2 * s->Q * NP <= kMaxBlockDof && E * 2 <= s->K && s->K / (E * 2) >= kMinBlocks &&
+  while ((int64_t)E * 2 * s->Q * NP <= kMaxBlockDof && E * 2 <= s->K &&
          stage32_lds_bytes(s->p, E * 2, s->Q, bf, ref) <= kFusedLdsLimit)
     E *= 2;
   if (s->forced_E > 0) E = s->forced_E;
@@ -257,7 +252,6 @@ void choose_tiling(dgbgk_solver *s) {
   // the persistent kernel takes one velocity row per thread
   const bool row_cap = s->tiling_mode == 4 && s->p <= kStreamMaxP;
   while (E * 2 <= G && (int64_t)E * 2 * s->Q * NP <= kMaxBlockDof && E * 2 <= s->K &&
-         s->K / (E * 2) >= kMinBlocks &&
          (!row_cap || (int64_t)E * 2 * s->Q <= kBlock) &&
          stage_lds_bytes(s->p, E * 2, s->Q) <= kFusedLdsLimit)
     E *= 2;

@@ -117,7 +117,6 @@ STRIP_CASES = [c for c in RHS_CASES if "_strips_" in c[0]]
 def test_strip_ordered_blocks_steps_match_oracle(oracle_mod, name, spec, tiling):
     _say(f"[gpu] strip-ordered blocks, 20 steps: {name}")
     g, o = _pair(oracle_mod, spec, tiling)
-    g.set_block_elements(1 if "E1" in name else 2)
     assert g.tiling()["elems_per_group"] == (1 if "E1" in name else 2)
     f = workloads.perturbed_state(29, o.w, o.K, o.Np, amp=0.05)
     g.set_state(f)
