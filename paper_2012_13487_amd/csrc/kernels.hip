@@ -395,24 +395,10 @@ __device__ __forceinline__ RowVel row_vel(const StageArgs &a, int qg) {
   return v;
 }
 
-#ifndef DGBGK_STAGE1_ROWS
-#define DGBGK_STAGE1_ROWS 1
-#endif
-// Stage 1 of RK4 in velocity-tiled blocks writes both of its outputs from the
-// row phase: the accumulator f_s + dt/6 k straight from registers to HBM, the
-// stage output f_s + dt/2 k into the LDS row for the coalesced store, so that
-// the update pass need not read f_s again (the tile in LDS holds L(f) by
-// then).  Measured: 2633 -> 2577 us per stage on the 128x128 p = 4 NC 24x24
-// cavity; the fused one-element blocks of the 64x64 p = 3 cavity are faster
-// without it (104 against 112 us: the row-wise stores of the accumulator
-// scatter over 128-byte lines).
-constexpr bool kStage1Rows = DGBGK_STAGE1_ROWS != 0;
-
-template <int P, bool ROW1 = false>
+template <int P>
 __device__ __forceinline__ void row_rhs(const StageArgs &a, double *row, const double *mm,
                                         const double *rwe, const RowVel &rv, int nbx, int nby,
-                                        const double (&px)[P + 1], const double (&py)[P + 1],
-                                        double *acc_row = nullptr) {
+                                        const double (&px)[P + 1], const double (&py)[P + 1]) {
   using Sh = Shape<P>;
   constexpr int N1 = Sh::N1, NP = Sh::NP, NFP = Sh::NFP;
   const double cx = rv.cx, cy = rv.cy, wq = rv.wq;
@@ -476,30 +462,6 @@ __device__ __forceinline__ void row_rhs(const StageArgs &a, double *row, const d
     const double feq = wq * m4[2] * (m4[3] + eu * (a.theta_inv + eu * a.half_theta2_inv));
     kk[nn] += (feq - f[nn]) * a.inv_tau;
   }
-  if constexpr (ROW1) {
-    // acc = f + dt/6 k to HBM, out = f + dt/2 k to the LDS row (rk_one, MODE 1)
-    const double ca = a.c_acc, co = a.c_out;
-#pragma unroll
-    for (int nn = 0; nn < NP; ++nn) {
-      const double an = f[nn] + ca * kk[nn];
-      kk[nn] = f[nn] + co * kk[nn];
-      f[nn] = an;
-    }
-    if (Sh::VEC) {
-#pragma unroll
-      for (int c = 0; c < NP / 2; ++c) {
-        const double2v v = {f[2 * c], f[2 * c + 1]};
-        if (a.stream_nt) __builtin_nontemporal_store(v, reinterpret_cast<double2v *>(acc_row + 2 * c));
-        else *reinterpret_cast<double2v *>(acc_row + 2 * c) = v;
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < NP; ++c) {
-        if (a.stream_nt) __builtin_nontemporal_store(f[c], acc_row + c);
-        else acc_row[c] = f[c];
-      }
-    }
-  }
   if (Sh::VEC) {
 #pragma unroll
     for (int c = 0; c < NP / 2; ++c)
@@ -559,8 +521,7 @@ __device__ __forceinline__ void update_rows(const StageArgs &a, const double *ti
       go[u] = e * QNP + q * NP + CW * w;
       if (ok[u]) kv[u] = lds_get<V>(tile + (q * E + e) * S + CW * w);
     }
-    constexpr bool LDS_OUT = false;  // fused blocks: the update pass reads f_s again
-    if (MODE != 0 && !LDS_OUT) {
+    if (MODE != 0) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (ok[u]) x[u] = ld_once<NT, V>(xr + go[u]);
@@ -574,13 +535,9 @@ __device__ __forceinline__ void update_rows(const StageArgs &a, const double *ti
     for (int u = 0; u < U; ++u) {
       if (!ok[u]) continue;
       V o, an;
-      if constexpr (LDS_OUT) {
-        o = kv[u];
-      } else {
-        rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
-      }
+      rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
       *reinterpret_cast<V *>(outr + go[u]) = o;
-      if (MODE == 2 || (MODE == 1 && !LDS_OUT)) st_once<NT, V>(accr + go[u], an);
+      if (MODE == 1 || MODE == 2) st_once<NT, V>(accr + go[u], an);
     }
   }
 }
@@ -613,8 +570,7 @@ __device__ __forceinline__ void update_pass(const StageArgs &a, const double *ti
     go[u] = e * QNP + q * NP + CW * w;
     if (ok[u]) kv[u] = lds_get<V>(tile + (q * E + e) * S + CW * w);
   }
-  constexpr bool LDS_OUT = MODE == 1 && kStage1Rows;  // the LDS tile holds the output
-  if (MODE != 0 && !LDS_OUT) {
+  if (MODE != 0) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (ok[u]) x[u] = ld_once<NT, V>(xr + go[u]);
@@ -628,19 +584,93 @@ __device__ __forceinline__ void update_pass(const StageArgs &a, const double *ti
   for (int u = 0; u < U; ++u) {
     if (!ok[u]) continue;
     V o, an;
-    if constexpr (LDS_OUT) {
-      o = kv[u];
-    } else {
-      rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
-    }
+    rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
     *reinterpret_cast<V *>(outr + go[u]) = o;
-    if (MODE == 2 || (MODE == 1 && !LDS_OUT)) st_once<NT, V>(accr + go[u], an);
-    if (keep && !LDS_OUT) {  // the output replaces L(f) at the same LDS position (this thread's own)
+    if (MODE == 1 || MODE == 2) st_once<NT, V>(accr + go[u], an);
+    if (keep) {  // the output replaces L(f) at the same LDS position (this thread's own)
       const int c = c0 + u * nthr;
       int q, e, w;
       split_access<CPE>(c, Qb, E, q, e, w);
       lds_put(keep + (q * E + e) * S + CW * w, o);
     }
+  }
+}
+
+// Phase 4 of a velocity tile whose output's moment partials the next stage
+// reads.  Thread t takes node n = t % NP of the velocity rows g, g + G, g + 2G,
+// ... (g = t / NP, G = nthr / NP groups): a wavefront's lanes cover
+// consecutive nodes of consecutive rows, so the accesses stay coalesced, and
+// each thread sums the moment weights (1, e_x, e_y, the outgoing normal
+// speeds) times its outputs in registers; the groups' sums are then added in
+// LDS in a fixed order and written to pout.  The tile must hold 7 G NP
+// doubles (the caller checks).
+template <int P, int MODE, bool NT>
+__device__ __forceinline__ void update_columns(const StageArgs &a, double *tile, const double *xr,
+                                               double *accr, double *outr, int Qb, int q0, int tid,
+                                               int nthr, double *po) {
+  using Sh = Shape<P>;
+  constexpr int NP = Sh::NP, S = Sh::S;
+  constexpr int U = 8;
+  const int G = nthr / NP;
+  const int g = tid / NP, n = tid - g * NP;
+  const double cacc = a.c_acc, cout = a.c_out;
+  double sm[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (g < G) {
+    for (int qa = g; qa < Qb; qa += G * U) {
+      double kv[U], x[U], y[U], cx[U], cy[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = qa + u * G;
+        if (q < Qb) {
+          kv[u] = tile[q * S + n];
+          cx[u] = a.vel[q0 + q];
+          cy[u] = a.vel[a.Q + q0 + q];
+        }
+      }
+      if (MODE != 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int q = qa + u * G;
+          if (q < Qb) x[u] = ld_once<NT, double>(xr + (size_t)q * NP + n);
+        }
+      }
+      if (MODE == 2) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int q = qa + u * G;
+          if (q < Qb) y[u] = ld_once<NT, double>(accr + (size_t)q * NP + n);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = qa + u * G;
+        if (q >= Qb) continue;
+        double o, an = 0.0;
+        rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
+        outr[(size_t)q * NP + n] = o;
+        if (MODE == 1 || MODE == 2) st_once<NT, double>(accr + (size_t)q * NP + n, an);
+        const double ex = cx[u], ey = cy[u];
+        sm[0] += o;
+        sm[1] += ex * o;
+        sm[2] += ey * o;
+        sm[3] += (ey < 0.0 ? -ey : 0.0) * o;
+        sm[4] += (ex > 0.0 ? ex : 0.0) * o;
+        sm[5] += (ey > 0.0 ? ey : 0.0) * o;
+        sm[6] += (ex < 0.0 ? -ex : 0.0) * o;
+      }
+    }
+  }
+  __syncthreads();  // every tile value is consumed: the groups' sums go there
+  if (g < G) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) tile[(g * 7 + c) * NP + n] = sm[c];
+  }
+  __syncthreads();
+  if (tid < 7 * NP) {
+    const int c = tid / NP, n2 = tid - c * NP;
+    double v = 0.0;
+    for (int gg = 0; gg < G; ++gg) v += tile[(gg * 7 + c) * NP + n2];
+    po[c * NP + n2] = v;
   }
 }
 
@@ -780,11 +810,7 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
     const int nbx = nbr[e * 4 + (rv.cx > 0.0 ? 3 : 1)], nby = nbr[e * 4 + (rv.cy > 0.0 ? 0 : 2)];
     double px[NFP], py[NFP];
     row_traces<P>(a, qg, k0 + e, nbx, nby, px, py);
-    if constexpr (MODE == 1 && kStage1Rows && !FUSED)
-      row_rhs<P, true>(a, tile + r * S, mom + e * NP * 4, rw + e * 4 * NFP, rv, nbx, nby, px, py,
-                       a.acc + (size_t)(k0 + e) * QNP + (size_t)qg * NP);
-    else
-      row_rhs<P>(a, tile + r * S, mom + e * NP * 4, rw + e * 4 * NFP, rv, nbx, nby, px, py);
+    row_rhs<P>(a, tile + r * S, mom + e * NP * 4, rw + e * 4 * NFP, rv, nbx, nby, px, py);
   }
   __syncthreads();
 
@@ -793,6 +819,11 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
     const double *xr = (MODE == 1 ? a.fs : MODE == 2 ? a.fn : a.acc) + boff;
     double *accr = a.acc + boff;
     double *outr = a.out + boff;
+    if (MODE != 0 && a.pout && E == 1 && 7 * (nthr / NP) * NP <= Qb * S) {
+      update_columns<P, MODE, NTM == 1>(a, tile, xr, accr, outr, Qb, q0, tid, nthr,
+                                        a.pout + (((size_t)tile_y * a.K + k0) * 7) * NP);
+      return;
+    }
     double *keep = (MODE != 0 && a.pout) ? tile : nullptr;
     for (int c0 = tid; c0 < nch; c0 += nthr * U)
       update_pass<P, MODE, NTM == 1>(a, tile, xr, accr, outr, c0, Qb, E, Eb, nch, full, tid, nthr,
