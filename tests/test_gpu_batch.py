@@ -187,9 +187,10 @@ def test_autotune_keeps_parity(oracle_mod):
         g.set_block_elements(3)  # not a power of two
 
 
-def test_full_mixed_batch_sampled_members():
+def test_full_mixed_batch_sampled_members(oracle_mod):
     """The 64-problem mixed batch (seed 0) at full size in FP64, stepped twice
-    as the benchmark times it; three sampled members against solo runs."""
+    as the benchmark times it (four lanes, graph replay); three sampled members
+    against solo runs (bit for bit) and against the oracle (1e-12)."""
     _say("[gpu] full mixed batch, 64 problems")
     specs = workloads.batch_instances(seed=0, n=64)
     members = [binding.Solver.from_spec(s, stream="torch") for s in specs]
@@ -207,6 +208,17 @@ def test_full_mixed_batch_sampled_members():
         g.step(2, dts[i])
         assert np.array_equal(g.get_state(), members[i].get_state())
         g.close()
+        o = oracle_mod.Oracle.from_spec(specs[i])
+        o.init_equilibrium()
+        o.rk4(2, dts[i])
+        ro, uxo, uyo = o.moments()
+        rg, uxg, uyg = members[i].moments()
+        er = float(np.max(np.abs(rg - ro)) / np.max(np.abs(ro)))
+        u_o = np.stack([uxo, uyo])
+        eu = float(np.max(np.abs(np.stack([uxg, uyg]) - u_o)) / np.max(np.abs(u_o)))
+        _say(f"    vs oracle: err rho {er:.2e} u {eu:.2e}")
+        assert er < 1e-12 and eu < 1e-12, (er, eu)
+        del o
     b.close()
     for g in members:
         g.close()

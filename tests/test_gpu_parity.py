@@ -64,6 +64,9 @@ RHS_CASES = [
     ("cavity_5x4_p4_nc12_fused", workloads.cavity(n=5, ny=4, p=4, m=12, lid=0.15, kn=0.4), None),
     ("cavity_4x3_p6_nc5_fused", workloads.cavity(n=4, ny=3, p=6, m=5, lid=0.1), None),
     ("couette_3x2_p7_gh4_fused", workloads.couette(nx=3, ny=2, p=7), None),
+    # the largest velocity set the ABI takes (4096 = NC 64 x 64): velocity tiles with
+    # a moments pass before every stage (more tiles than partials are kept for)
+    ("cavity_2x2_p2_nc64_maxQ", workloads.cavity(n=2, p=2, m=64, lid=0.1), None),
 ]
 
 
@@ -130,6 +133,23 @@ def test_strip_ordered_blocks_steps_match_oracle(oracle_mod, name, spec, tiling)
 
 
 FUSED_HIGH_ORDER = [c for c in RHS_CASES if c[0].endswith("_fused")]
+
+
+def test_largest_velocity_set_steps_match_oracle(oracle_mod):
+    """Q = 4096 (NC 64 x 64) on a 2x2 p = 2 cavity: 10 RK4 steps in the
+    automatic (velocity-tiled) form against the oracle."""
+    _say("[gpu] largest velocity set, 10 steps")
+    spec = workloads.cavity(n=2, p=2, m=64, lid=0.1)
+    g, o = _pair(oracle_mod, spec)
+    assert g.Q == 4096 and g.tiling()["fused"] == 0
+    f = workloads.perturbed_state(47, o.w, o.K, o.Np, amp=0.05)
+    g.set_state(f)
+    o.set_state(f)
+    dt = o.stable_dt(0.2)
+    g.step(10, dt)
+    o.rk4(10, dt)
+    er, eu = _moment_errors(g, o)
+    assert er < TOL and eu < TOL, (er, eu)
 
 
 @pytest.mark.parametrize("name,spec,tiling", FUSED_HIGH_ORDER, ids=[c[0] for c in FUSED_HIGH_ORDER])
