@@ -229,13 +229,14 @@ SERVE_REDUCED = dict(n_range=(16, 28), p_choices=(2, 3), kn_log10=(-0.5, 1.0), m
 SERVE_FULL = dict(n_range=(16, 96), p_choices=(2, 3, 4), kn_log10=(-1.0, 1.0), m_range=(8, 24))
 
 
-def serving(n_requests, dist, time_limit_s, label, precisions=("fp64", "fp32_ref")):
+def serving(n_requests, dist, time_limit_s, label, precisions=("fp64", "fp32_ref"), max_active=16):
     """Steady-state serving (continuous batching) of a seeded Poisson stream
     (rate 20/s, seed 1) of requests drawn from the mixed-problem distribution
     `dist` (seed 2), each run from rest to residual 1e-6: served DOF-updates/s
     and p50/p99 latency (arrival to residual 1e-6) for plain FP64 and for the
     reference form (FP32 correction streamed, FP64 reference folded at every
-    residual check).  Requests still running at the time limit count in
+    residual check).  At most max_active requests run at once (the others wait
+    for a slot); requests still running at the time limit count in
     `dof_updates_all_per_s` and not in `value`."""
     import workloads
     from paper_2012_13487_amd import Server
@@ -248,10 +249,11 @@ def serving(n_requests, dist, time_limit_s, label, precisions=("fp64", "fp32_ref
                        f"[{10 ** dist['kn_log10'][0]:.3g}, {10 ** dist['kn_log10'][1]:.3g}], "
                        f"D2Q16 GH or NC MxM with M in {dist['m_range'][0]}..{dist['m_range'][1]}",
            "residual_target": 1e-6, "check_every": 50, "time_limit_s": time_limit_s,
+           "max_active": max_active, "hbm_budget_bytes": 64 << 30,
            "offered_requests_per_s": 20.0}
     for prec in precisions:
-        sv = Server(hbm_budget=64 << 30, max_active=64, precision=prec, residual_target=1e-6,
-                    check_every=50, max_steps=5_000_000, graph=True)
+        sv = Server(hbm_budget=64 << 30, max_active=max_active, precision=prec,
+                    residual_target=1e-6, check_every=50, max_steps=5_000_000, graph=True)
         ids = [sv.submit(r, a) for r, a in zip(reqs, arrivals)]
         # in slices of at most a minute (the server resumes where it stopped),
         # reporting progress between them
@@ -514,7 +516,8 @@ def main():
     if args.serving_full:
         print(json.dumps({"serving_full": serving(
             args.serving_full, SERVE_FULL, args.serving_time_limit,
-            "the config-4 mixed-problem distribution at full size, request count capped")}),
+            "the config-4 mixed-problem distribution at full size, request count capped",
+            max_active=64)}),
             flush=True)
         return
     spec = workloads.CAVITY_64x64_P3_NC16

@@ -384,10 +384,15 @@ int dgbgk_implicit_step_noalloc(dgbgk_solver *s, int32_t scheme, int64_t nsteps,
  *
  * A batch advances n solvers (any mix of meshes, orders, velocity sets, Kn,
  * walls and precisions) in lock step: each RK4 stage is one persistent kernel
- * launch per class of (precision, order p, access width, LDS size) that walks
- * a device work list of (problem, element block) items and reads each
- * problem's arguments (state pointers, mesh and velocity tables, tau, walls,
- * and its own dt) from a device descriptor table.  A member of 2^22 DOF
+ * launch per class of (precision, order p, access width, contraction,
+ * reference form, LDS size) that walks a device work list of (problem, element
+ * block) items and reads each problem's arguments (state pointers, mesh and
+ * velocity tables, tau, walls, and its own dt) from a device descriptor table.
+ * Classes (and the large members below) are independent chains of launches:
+ * the batch spreads them over up to four streams of its own, forked from and
+ * joined to the batch's stream around every call (and inside a captured
+ * graph), so that work enqueued later on the batch's stream sees every
+ * member's steps complete.  A member of 2^22 DOF
  * (K Np Q) or more fills the GPU by itself and runs its own single-problem
  * stage kernels, in its own decomposition, in the same step instead (with such
  * members a change of dt re-captures the step graph).  The members keep their own
