@@ -525,8 +525,8 @@ int run_stage(dgbgk_solver *s, int stage, const void *fs_, void *out_, double dt
   a.out = out;
   a.stage = stage;
   a.rhow_out = rhow_out;
-  a.pin = s->fused ? nullptr : pin;
-  a.pout = s->fused ? nullptr : pout;
+  a.pin = pin;
+  a.pout = pout;
   rk_coefficients(stage, dt, a.c_acc, a.c_out);
   if (s->persistent) {
     const int groups = (int)std::min<int64_t>(s->nblk, (int64_t)s->num_cu);
@@ -1005,23 +1005,51 @@ namespace {
 // One RK4 step.  Registers: f_n, acc, and two stage buffers A/B so that a
 // stage never overwrites the state its neighbours still read.
 bool uses_partials(const dgbgk_solver *s) {
-  return s->prec == DGBGK_FP64 && !s->fused && s->ntiles <= kMaxPartialTiles && s->d_part[0];
+  if (s->prec != DGBGK_FP64 || !s->d_part[0]) return false;
+  if (!s->fused) return s->ntiles <= kMaxPartialTiles;
+  return s->E == 1 && !s->persistent && handoff_moments(s->p);
 }
 
-// Velocity-tiled FP64 stages hand the moment partials of their output to the
-// next stage (slots P0 -> P1 -> P0 -> P1 -> P0), so only the first stage
-// after f_n was set from outside a step reduces the moments in a separate pass.
+// Velocity-tiled FP64 stages, and fused ones of one element per work-group
+// (orders 1 and 3), hand the moment partials of their output to the next
+// stage.  Slots: stage 1 reads P0 and writes P1, then P1 -> P0, P0 -> P1,
+// P1 -> P0, so P0 holds the partials of f_n between steps (stage 0 reads it).
+void stage_partials(const dgbgk_solver *s, int stage, const double *&pin, double *&pout) {
+  pin = nullptr;
+  pout = nullptr;
+  if (!uses_partials(s)) return;
+  double *P0 = s->d_part[0], *P1 = s->d_part[1];
+  const bool odd = stage == 1 || stage == 3;
+  pin = stage == 2 || stage == 4 ? P1 : P0;
+  if (stage != 0) pout = odd ? P1 : P0;
+}
+
+// The partials of f_n in P0 (the full moment rows in tile 0, zeros in the
+// others) where they are stale: after f_n was set from outside a step.
+int ensure_partials(dgbgk_solver *s) {
+  if (!uses_partials(s) || s->part_valid) return DGBGK_OK;
+  hipError_t e = launch_moment_rows(s->d_fn, s->d_vel, (int)s->K, s->Np, s->Q,
+                                    s->fused ? 1 : s->ntiles, s->d_part[0], s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "moment rows kernel");
+  s->part_valid = true;
+  return DGBGK_OK;
+}
+
 int enqueue_rk4_step(dgbgk_solver *s, double dt) {
   int rc;
   void *fn = s->d_fn, *A = s->d_a, *B = s->d_b;
   if (uses_partials(s)) {
-    double *P0 = s->d_part[0], *P1 = s->d_part[1];
-    if ((rc = run_stage(s, 1, fn, A, dt, nullptr, s->part_valid ? P0 : nullptr, P1))) return rc;
-    s->part_valid = false;
-    if ((rc = run_stage(s, 2, A, B, dt, nullptr, P1, P0))) return rc;
-    if ((rc = run_stage(s, 3, B, A, dt, nullptr, P0, P1))) return rc;
-    if ((rc = run_stage(s, 4, A, fn, dt, nullptr, P1, P0))) return rc;
-    s->part_valid = true;
+    if ((rc = ensure_partials(s))) return rc;
+    void *const io[5] = {fn, A, B, A, fn};
+    for (int st = 1; st <= 4; ++st) {
+      const double *pin;
+      double *pout;
+      stage_partials(s, st, pin, pout);
+      if ((rc = run_stage(s, st, io[st - 1], io[st], dt, nullptr, pin, pout))) {
+        s->part_valid = false;
+        return rc;
+      }
+    }
     return DGBGK_OK;
   }
   if ((rc = run_stage(s, 1, fn, A, dt))) return rc;
@@ -1186,9 +1214,12 @@ int dgbgk_wall_density(dgbgk_solver *s, const double *f, double *out, size_t cou
 }
 
 static int residual_enqueue(dgbgk_solver *s) {
-  int rc = run_stage(s, 0, s->d_fn, s->d_b, 0.0, nullptr,
-                     uses_partials(s) && s->part_valid ? s->d_part[0] : nullptr);
+  int rc = ensure_partials(s);
   if (rc) return rc;
+  const double *pin;
+  double *pout;
+  stage_partials(s, 0, pin, pout);
+  if ((rc = run_stage(s, 0, s->d_fn, s->d_b, 0.0, nullptr, pin))) return rc;
   hipError_t e = launch_fill_u64(s->d_u64, 1, 0ull, s->stream);
   if (e == hipSuccess)
     e = is_fp32(s->prec)
@@ -2094,10 +2125,25 @@ void fill_descriptors(dgbgk_batch *b, const double *dt) {
           a.c_acc = ca;
           a.c_out = co;
           a.stream_nt = nt;
+          stage_partials(s, stage, a.pin, a.pout);
           std::memcpy(dst, &a, sizeof a);
         }
       }
   }
+}
+
+// The members' stages read the partials of f_n from P0: fill those that are
+// stale, on the batch's stream.
+int batch_partials(dgbgk_batch *b) {
+  for (size_t i = 0; i < b->s.size(); ++i) {
+    dgbgk_solver *s = b->s[i];
+    hipStream_t own = s->stream;
+    s->stream = b->stream;
+    const int rc = ensure_partials(s);
+    s->stream = own;
+    if (rc) return bfail(b, rc, "member %zu: %s", i, s->err.c_str());
+  }
+  return DGBGK_OK;
 }
 
 int upload_descriptors(dgbgk_batch *b) {
@@ -2133,8 +2179,10 @@ int launch_solo(dgbgk_batch *b, int i, int stage, hipStream_t st) {
   stage_buffers(s, stage, fs, out);
   hipStream_t own = s->stream;
   s->stream = st;
-  if (stage != 0) s->part_valid = false;  // these stages reduce their moments in passes
-  const int rc = run_stage(s, stage, fs, out, b->dt_loaded[i]);
+  const double *pin;
+  double *pout;
+  stage_partials(s, stage, pin, pout);  // P0 is current: the batch filled it before its steps
+  const int rc = run_stage(s, stage, fs, out, b->dt_loaded[i], nullptr, pin, pout);
   s->stream = own;
   if (rc) return bfail(b, rc, "member %d: %s", i, s->err.c_str());
   return DGBGK_OK;
@@ -2395,6 +2443,8 @@ int dgbgk_batch_step(dgbgk_batch *b, int64_t nsteps, const double *dt) {
     if (!b->solo.empty()) drop_graph(b);
   }
   if (nsteps == 0) return DGBGK_OK;
+  if ((rc = batch_partials(b))) return rc;
+  for (auto *s : b->s) s->part_valid = false;  // until every step is enqueued
   const int k = b->graph_steps;
   if (k > 0 && ((nsteps >= k && !b->exec) || (nsteps % k != 0 && !b->exec1))) {
     // one eager step first: it sets the kernels' LDS attributes outside the capture
@@ -2418,7 +2468,10 @@ int dgbgk_batch_step(dgbgk_batch *b, int64_t nsteps, const double *dt) {
   } else if ((rc = enqueue_steps(b, nsteps - it))) {
     return rc;
   }
-  for (auto *s : b->s) s->steps += nsteps;
+  for (auto *s : b->s) {
+    s->steps += nsteps;
+    s->part_valid = uses_partials(s);  // each step ends with the partials of f_n in P0
+  }
   return DGBGK_OK;
 }
 
@@ -2435,9 +2488,10 @@ int dgbgk_batch_residuals(dgbgk_batch *b, double *r) {
   // kernels for large members), then one reduction launch per member into the
   // batch's accumulators and a single copy to the host
   unsigned long long *acc = (unsigned long long *)(b->dev + b->off_res);
+  int rc = batch_partials(b);
+  if (rc) return rc;
   hipError_t e = launch_fill_u64(acc, n, 0ull, b->stream);
   if (e != hipSuccess) return bfail(b, DGBGK_EDEVICE, "fill kernel: %s", hipGetErrorString(e));
-  int rc = DGBGK_OK;
   for (const auto &c : b->cls)
     if ((rc = launch_class(b, c, 0, b->stream))) return rc;
   for (int i : b->solo)

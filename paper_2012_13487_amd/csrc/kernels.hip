@@ -674,6 +674,124 @@ __device__ __forceinline__ void update_columns(const StageArgs &a, double *tile,
   }
 }
 
+// Whether one-element fused blocks of order P hand their output's moments to
+// the next stage: each thread's accesses of phase 4 then stay on one column
+// of CW nodes, and the four wavefronts' sums fit the partial-product area.
+template <int P>
+__host__ __device__ constexpr bool handoff_order() {
+  constexpr int NP = (P + 1) * (P + 1), CPE = NP % 2 == 0 ? NP / 2 : NP;
+  return kBlock % CPE == 0 && 64 % CPE == 0 && 4 * 7 * NP <= 4 * 7 * 16;
+}
+
+static_assert(handoff_order<1>() == handoff_moments(1) && handoff_order<2>() == handoff_moments(2) &&
+                  handoff_order<3>() == handoff_moments(3) && handoff_order<4>() == handoff_moments(4) &&
+                  handoff_order<5>() == handoff_moments(5) && handoff_order<6>() == handoff_moments(6) &&
+                  handoff_order<7>() == handoff_moments(7) && handoff_order<8>() == handoff_moments(8),
+              "the host's choice of orders that hand over moments matches the kernel's");
+
+// Phase 4 of a one-element fused block (the accesses of update_rows) that
+// also sums the moments of its output over the velocities, per node, for the
+// next stage: rows 0..2 of po (1, e_x, e_y), and rows 3..6 (the outgoing
+// normal speed at each wall) when WALL.  Each thread keeps one column of CW
+// nodes; the column sums are reduced across the lanes of a wavefront, then
+// across the wavefronts in red (4 x 7 x NP doubles).
+template <int P, int MODE, bool NT, bool WALL>
+__device__ __forceinline__ void update_rows_handoff(const StageArgs &a, const double *tile, size_t boff,
+                                                    int Qb, int tid, int nthr, double *red,
+                                                    double *po) {
+  using Sh = Shape<P>;
+  constexpr int NP = Sh::NP, S = Sh::S;
+  constexpr int CW = Sh::VEC ? 2 : 1;
+  constexpr int CPE = NP / CW;
+  constexpr int U = 4;  // (8 measured slower: more registers, fewer resident work-groups)
+  constexpr int W = WALL ? 7 : 3;
+  using V = typename std::conditional<Sh::VEC, double2v, double>::type;
+  const double cacc = a.c_acc, cout = a.c_out;
+  const double *xr = (MODE == 1 ? a.fs : MODE == 2 ? a.fn : a.acc) + boff;
+  double *accr = a.acc + boff;
+  double *outr = a.out + boff;
+  const int w = tid % CPE;  // nthr is a multiple of CPE: the column never changes
+  const int nch = Qb * CPE;
+  double sm[W][CW];
+#pragma unroll
+  for (int c = 0; c < W; ++c)
+#pragma unroll
+    for (int j = 0; j < CW; ++j) sm[c][j] = 0.0;
+  for (int c0 = tid; c0 < nch; c0 += nthr * U) {
+    V kv[U], x[U], y[U];
+    double ex[U], ey[U];
+    int go[U];
+    bool ok[U];
+    const bool all = c0 - tid + U * nthr <= nch;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * nthr;
+      const int q = c / CPE;
+      ok[u] = all || c < nch;
+      go[u] = q * NP + CW * w;
+      if (ok[u]) {
+        kv[u] = lds_get<V>(tile + q * S + CW * w);
+        ex[u] = a.vel[q];
+        ey[u] = a.vel[a.Q + q];
+      }
+    }
+    if (MODE == 1 || MODE == 2 || MODE == 4) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ok[u]) x[u] = ld_once<NT, V>(xr + go[u]);
+    }
+    if (MODE == 2) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ok[u]) y[u] = ld_once<NT, V>(accr + go[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!ok[u]) continue;
+      V o, an;
+      rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
+      *reinterpret_cast<V *>(outr + go[u]) = o;
+      if (MODE == 1 || MODE == 2) st_once<NT, V>(accr + go[u], an);
+      const double *ov = reinterpret_cast<const double *>(&o);
+      double wt[W];
+      wt[0] = 1.0;
+      wt[1] = ex[u];
+      wt[2] = ey[u];
+      if (WALL) {
+        wt[3 % W] = ey[u] < 0.0 ? -ey[u] : 0.0;
+        wt[4 % W] = ex[u] > 0.0 ? ex[u] : 0.0;
+        wt[5 % W] = ey[u] > 0.0 ? ey[u] : 0.0;
+        wt[6 % W] = ex[u] < 0.0 ? -ex[u] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < W; ++c)
+#pragma unroll
+        for (int j = 0; j < CW; ++j) sm[c][j] += wt[c] * ov[j];
+    }
+  }
+  // lanes with the same column are CPE apart within a wavefront
+#pragma unroll
+  for (int m = CPE; m < 64; m <<= 1)
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+#pragma unroll
+      for (int j = 0; j < CW; ++j) sm[c][j] += __shfl_xor(sm[c][j], m);
+  const int wave = tid >> 6, lane = tid & 63;
+  if (lane < CPE) {
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+#pragma unroll
+      for (int j = 0; j < CW; ++j) red[(wave * 7 + c) * NP + CW * lane + j] = sm[c][j];
+  }
+  __syncthreads();
+  if (tid < W * NP) {
+    const int c = tid / NP, n = tid - c * NP;
+    double v = 0.0;
+    for (int wv = 0; wv < (nthr >> 6); ++wv) v += red[(wv * 7 + c) * NP + n];
+    po[c * NP + n] = v;
+  }
+}
+
 // MODE: 0 writes L(f_s); 1 first RK4 stage; 2 second and third; 4 fourth.
 // FUSED: the block reduces its own moments and wall densities (a.fused).
 // One element block blk and velocity tile tile_y of the stage, by one
@@ -681,7 +799,7 @@ __device__ __forceinline__ void update_columns(const StageArgs &a, double *tile,
 // NTM: 0 the cache policy of phase 4 is chosen at run time (a.stream_nt);
 // 1 / 2 it is fixed to non-temporal / normal at compile time.
 // EFIX: elements per work-group fixed at compile time (0: a.E at run time).
-template <int P, int MODE, bool FUSED, int NTM, int EFIX = 0>
+template <int P, int MODE, bool FUSED, int NTM, int EFIX = 0, bool HO = false>
 __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int tile_y) {
   using Sh = Shape<P>;
   constexpr int NP = Sh::NP, NFP = Sh::NFP, S = Sh::S;
@@ -717,6 +835,26 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
     const int e = tid >> 2, fc = tid & 3;
     nbr[tid] = e < Eb ? neighbour(k0 + e, fc, a) : -1;
   }
+  // one-element fused blocks read the moments of f_s handed over by the stage
+  // that wrote it; the loads are issued before the tile's
+  const bool handoff = FUSED && E == 1 && handoff_order<P>();
+  const bool pin1 = HO || (handoff && a.pin != nullptr);
+  // (rows 3..6 of the moments, the wall sums, exist only where the element
+  // has a wall face; the flag is formed by every thread: measured faster than
+  // by the loading threads alone)
+  const bool we = handoff && a.wall_mask != 0 &&
+                  (neighbour(k0, 0, a) < 0 || neighbour(k0, 1, a) < 0 || neighbour(k0, 2, a) < 0 ||
+                   neighbour(k0, 3, a) < 0);
+  double pv[7];
+  if (pin1 && tid < NP) {
+    const double *pp = a.pin + (size_t)k0 * 7 * NP + tid;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pv[c] = pp[c * NP];
+    if (we) {
+#pragma unroll
+      for (int c = 3; c < 7; ++c) pv[c] = pp[c * NP];
+    }
+  }
 
   // ---- 1. f_s of the block into LDS (coalesced, U accesses in flight) ----------
   const bool full = Eb == E;
@@ -744,13 +882,29 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
   __syncthreads();
 
   // ---- 2. node moments and diffuse-wall densities ----------------------------
-  if (FUSED) {
-    block_moments_mfma<P, 16>(tile, part, a.wmom + (size_t)q0 * 16, E, Qb, Eb, tid, nthr);
-    __syncthreads();
-    block_moments_combine<P>(a, part, mom, rw, nbr, E, Eb, k0, tid);
+  if (pin1) {
+    if (tid < NP) {
+      const int n2 = tid;
+      const double rho = pv[0], ux = pv[1] / rho, uy = pv[2] / rho;
+      double *m = mom + n2 * 4;
+      m[0] = ux;
+      m[1] = uy;
+      m[2] = rho;
+      m[3] = 1.0 - (ux * ux + uy * uy) * a.half_theta_inv;
+      if (a.wall_mask != 0) {
+        constexpr int N1 = Sh::N1;
+        const int i2 = n2 % N1, j2 = n2 / N1;
+        const bool on[4] = {nbr[0] < 0 && j2 == 0, nbr[1] < 0 && i2 == P, nbr[2] < 0 && j2 == P,
+                            nbr[3] < 0 && i2 == 0};
+        const int fm[4] = {i2, j2, i2, j2};
+#pragma unroll
+        for (int fc = 0; fc < 4; ++fc)
+          if (on[fc]) rw[fc * NFP + fm[fc]] = pv[3 + fc] * a.wall_den_inv[fc];
+      }
+    }
   } else if (a.pin) {
-    // the moments of f_s summed from the velocity tiles' partials, written by
-    // the stage that produced f_s
+    // the moments of f_s summed from the velocity tiles' partials (one tile in
+    // the fused form), written by the stage that produced f_s
     if (tid < E * NP) {
       const int e2 = tid / NP, n2 = tid % NP;
       if (e2 < Eb) {
@@ -779,6 +933,10 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
         }
       }
     }
+  } else if (FUSED && !HO) {
+    block_moments_mfma<P, 16>(tile, part, a.wmom + (size_t)q0 * 16, E, Qb, Eb, tid, nthr);
+    __syncthreads();
+    block_moments_combine<P>(a, part, mom, rw, nbr, E, Eb, k0, tid);
   } else {
     if (tid < E * NP) {
       const int e2 = tid / NP, n2 = tid % NP;
@@ -852,6 +1010,19 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
         }
       }
     }
+  } else if (MODE != 0 && handoff && a.pout) {
+    // one-element blocks handing their output's moments to the next stage
+    double *po = a.pout + ((size_t)k0 * 7) * NP;
+    const bool wall_el = we;
+    if constexpr (handoff_order<P>()) {
+      if (a.stream_nt) {
+        if (wall_el) update_rows_handoff<P, MODE, true, true>(a, tile, boff, Qb, tid, nthr, part, po);
+        else update_rows_handoff<P, MODE, true, false>(a, tile, boff, Qb, tid, nthr, part, po);
+      } else {
+        if (wall_el) update_rows_handoff<P, MODE, false, true>(a, tile, boff, Qb, tid, nthr, part, po);
+        else update_rows_handoff<P, MODE, false, false>(a, tile, boff, Qb, tid, nthr, part, po);
+      }
+    }
   } else if (a.stream_nt) {
     update_rows<P, MODE, true>(a, tile, boff, Qb, E, Eb, nch, full, tid, nthr);
   } else {
@@ -866,7 +1037,9 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
   const int blk = strip_block(xcd_block(blockIdx.x, a.nblk), a.nx, a.log2E, a.nblk);
   // Code layouts chosen by measurement: the fused block with the run-time
   // cache policy, the velocity-tiled block with one copy per policy.
-  if constexpr (FK == 2)
+  if constexpr (FK == 3)
+    stage_block<P, MODE, true, 0, 1, true>(a, blk, blockIdx.y);
+  else if constexpr (FK == 2)
     stage_block<P, MODE, true, 0, 1>(a, blk, blockIdx.y);
   else if constexpr (FK == 1)
     stage_block<P, MODE, true, 0>(a, blk, blockIdx.y);
@@ -1152,6 +1325,34 @@ __global__ __launch_bounds__(256) void moments_kernel(const double *f, const dou
   if (wl) rhow[((size_t)k * 4 + 3) * NFP + jj] = hl * d3;
 }
 
+// Moment rows of a state for the stages that read their input's moments:
+// out[(k 7 + c) Np + n] = sum_q W[q][c] f[k][q][n] with W = (1, e_x, e_y, the
+// outgoing normal speed at the bottom, right, top, left wall), then zeros for
+// the partial slots of further velocity tiles.
+template <typename T>
+__global__ __launch_bounds__(256) void moment_rows_kernel(const T *f, const double *vel, int K, int Np,
+                                                          int Q, int ntiles, double *out) {
+  const size_t KNP = (size_t)K * Np;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= KNP) return;
+  const size_t k = i / Np, n = i % Np;
+  double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < Q; ++q) {
+    const double v = (double)f[(k * Q + q) * Np + n];
+    const double cx = vel[q], cy = vel[Q + q];
+    s[0] += v;
+    s[1] += cx * v;
+    s[2] += cy * v;
+    s[3] += (cy < 0.0 ? -cy : 0.0) * v;
+    s[4] += (cx > 0.0 ? cx : 0.0) * v;
+    s[5] += (cy > 0.0 ? cy : 0.0) * v;
+    s[6] += (cx < 0.0 ? -cx : 0.0) * v;
+  }
+  for (int c = 0; c < 7; ++c) out[(k * 7 + c) * Np + n] = s[c];
+  for (int t = 1; t < ntiles; ++t)
+    for (int c = 0; c < 7; ++c) out[(((size_t)t * K + k) * 7 + c) * Np + n] = 0.0;
+}
+
 // max that keeps NaN
 __device__ inline double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
 
@@ -1231,6 +1432,12 @@ hipError_t launch_stage_pm(const StageArgs &a, size_t lds, int ntiles, hipStream
   if (!a.fused) {
     if (a.E != 1) return hipErrorInvalidValue;  // velocity tiles hold one element
     return launch_stage_pmf<P, MODE, 0>(a, lds, ntiles, st);
+  }
+  if constexpr (handoff_order<P>()) {
+    // one-element blocks that read their input's moments (and, in RK4 stages,
+    // write their output's): a kernel without the matrix-core moment product,
+    // whose accumulators would cost a resident work-group per compute unit
+    if (a.E == 1 && a.pin && (MODE == 0 || a.pout)) return launch_stage_pmf<P, MODE, 3>(a, lds, ntiles, st);
   }
   return a.E == 1 ? launch_stage_pmf<P, MODE, 2>(a, lds, ntiles, st)
                   : launch_stage_pmf<P, MODE, 1>(a, lds, ntiles, st);
@@ -1368,6 +1575,22 @@ hipError_t launch_moments(const double *f, const double *vel, int K, int p, int 
   const unsigned nb = (unsigned)((KNP + 255) / 256);
   hipLaunchKernelGGL(moments_kernel, dim3(nb), dim3(256), 0, st, f, vel, K, p, Q, nx, ny,
                      wall_mask, den[0], den[1], den[2], den[3], rho, ux, uy, rhow);
+  return hipGetLastError();
+}
+
+hipError_t launch_moment_rows(const double *f, const double *vel, int K, int Np, int Q, int ntiles,
+                              double *out, hipStream_t st) {
+  const size_t KNP = (size_t)K * Np;
+  hipLaunchKernelGGL(moment_rows_kernel<double>, dim3((unsigned)((KNP + 255) / 256)), dim3(256), 0, st,
+                     f, vel, K, Np, Q, ntiles, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_moment_rows32(const float *f, const double *vel, int K, int Np, int Q, double *out,
+                                hipStream_t st) {
+  const size_t KNP = (size_t)K * Np;
+  hipLaunchKernelGGL(moment_rows_kernel<float>, dim3((unsigned)((KNP + 255) / 256)), dim3(256), 0, st,
+                     f, vel, K, Np, Q, 1, out);
   return hipGetLastError();
 }
 
