@@ -1329,16 +1329,16 @@ __global__ __launch_bounds__(256) void moments_kernel(const double *f, const dou
 // out[(k 7 + c) Np + n] = sum_q W[q][c] f[k][q][n] with W = (1, e_x, e_y, the
 // outgoing normal speed at the bottom, right, top, left wall), then zeros for
 // the partial slots of further velocity tiles.
-template <typename T>
-__global__ __launch_bounds__(256) void moment_rows_kernel(const T *f, const double *vel, int K, int Np,
+__global__ __launch_bounds__(256) void moment_rows_kernel(const double *f, const double *vel, int K, int Np,
                                                           int Q, int ntiles, double *out) {
   const size_t KNP = (size_t)K * Np;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= KNP) return;
   const size_t k = i / Np, n = i % Np;
   double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
   for (int q = 0; q < Q; ++q) {
-    const double v = (double)f[(k * Q + q) * Np + n];
+    const double v = f[(k * Q + q) * Np + n];
     const double cx = vel[q], cy = vel[Q + q];
     s[0] += v;
     s[1] += cx * v;
@@ -1581,16 +1581,8 @@ hipError_t launch_moments(const double *f, const double *vel, int K, int p, int 
 hipError_t launch_moment_rows(const double *f, const double *vel, int K, int Np, int Q, int ntiles,
                               double *out, hipStream_t st) {
   const size_t KNP = (size_t)K * Np;
-  hipLaunchKernelGGL(moment_rows_kernel<double>, dim3((unsigned)((KNP + 255) / 256)), dim3(256), 0, st,
+  hipLaunchKernelGGL(moment_rows_kernel, dim3((unsigned)((KNP + 255) / 256)), dim3(256), 0, st,
                      f, vel, K, Np, Q, ntiles, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_moment_rows32(const float *f, const double *vel, int K, int Np, int Q, double *out,
-                                hipStream_t st) {
-  const size_t KNP = (size_t)K * Np;
-  hipLaunchKernelGGL(moment_rows_kernel<float>, dim3((unsigned)((KNP + 255) / 256)), dim3(256), 0, st,
-                     f, vel, K, Np, Q, 1, out);
   return hipGetLastError();
 }
 

@@ -90,14 +90,12 @@ hipError_t launch_moments(const double *f, const double *vel, int K, int p, int 
 // output to the next stage (a.pin / a.pout of the fused form).
 __host__ __device__ constexpr bool handoff_moments(int p) { return p == 1 || p == 3; }
 
-// Moment rows of a state (FP64 or FP32 values, element-major): out[k][7][Np]
-// = sum over velocities of (1, e_x, e_y, outgoing normal speed at the bottom,
-// right, top, left wall) times f, the input moments of the stages that read
-// them (a.pin); the FP64 form also zeroes the slots of tiles 1..ntiles-1.
+// Moment rows of an FP64 state (element-major): out[k][7][Np] = sum over
+// velocities of (1, e_x, e_y, outgoing normal speed at the bottom, right, top,
+// left wall) times f, the input moments of the stages that read them (a.pin),
+// then zeros in the slots of tiles 1..ntiles-1.
 hipError_t launch_moment_rows(const double *f, const double *vel, int K, int Np, int Q, int ntiles,
                               double *out, hipStream_t stream);
-hipError_t launch_moment_rows32(const float *f, const double *vel, int K, int Np, int Q, double *out,
-                                hipStream_t stream);
 
 // Scaled max-norm of the moment rates of k = L(f): atomically max-reduced into
 // *result (bit pattern of a non-negative double; must be zeroed first).
