@@ -53,6 +53,12 @@ bool valid_precision(int precision) { return precision == DGBGK_FP64 || is_fp32(
 
 // State registers (FP64, or the FP32 deviation), an FP64 transfer buffer for
 // the FP32 precisions, then the small tables.
+// Velocity tiles whose moment partials a state of this precision keeps.
+int part_tiles(int precision, int Np) {
+  if (precision == DGBGK_FP64) return kMaxPartialTiles;
+  return (Np == 4 || Np == 16) ? 1 : 0;  // the orders that hand moments over (1 and 3)
+}
+
 Layout make_layout(int64_t K, int Np, int Nfp, int Q, int precision) {
   Layout L{};
   const size_t ndof = (size_t)K * Np * Q;
@@ -75,10 +81,11 @@ Layout make_layout(int64_t K, int Np, int Nfp, int Q, int precision) {
   L.fref = off; off += ref ? round_up(ndof * sizeof(double)) : 0;
   L.rref = off; off += ref ? round_up(ndof * sizeof(float)) : 0;
   L.mref = off; off += ref ? round_up((size_t)3 * K * Np * sizeof(double)) : 0;
-  // FP64 velocity-tiled stages: moment partials of two states, up to
-  // kMaxPartialTiles tiles each (the state a stage reads, the one it writes)
+  // moment partials of two states (the state a stage reads, the one it
+  // writes): FP64 up to kMaxPartialTiles velocity tiles each; FP32 storage one
+  // (one-element blocks of orders 1 and 3)
   L.part = off;
-  off += precision == DGBGK_FP64 ? 2 * round_up((size_t)kMaxPartialTiles * K * 7 * Np * sizeof(double)) : 0;
+  off += 2 * round_up((size_t)part_tiles(precision, Np) * K * 7 * Np * sizeof(double));
   L.total = off;
   return L;
 }
@@ -327,10 +334,9 @@ int ensure_device(dgbgk_solver *s) {
   s->d_mom = (double *)(b + s->lay.mom);
   s->d_rhow = (double *)(b + s->lay.rhow);
   s->d_u64 = (unsigned long long *)(b + s->lay.u64);
-  if (s->prec == DGBGK_FP64) {
+  if (const int pt = part_tiles(s->prec, s->Np)) {
     s->d_part[0] = (double *)(b + s->lay.part);
-    s->d_part[1] = (double *)(b + s->lay.part +
-                              round_up((size_t)kMaxPartialTiles * s->K * 7 * s->Np * sizeof(double)));
+    s->d_part[1] = (double *)(b + s->lay.part + round_up((size_t)pt * s->K * 7 * s->Np * sizeof(double)));
   }
   if (is_ref(s->prec)) {
     s->d_fref = (double *)(b + s->lay.fref);
@@ -485,7 +491,7 @@ void rk_coefficients(int stage, double dt, double &ca, double &co) {
 
 // One FP32 stage on deviation arrays.
 int run_stage32(dgbgk_solver *s, int stage, const float *fs, float *out, double dt,
-                double *rhow_out) {
+                double *rhow_out, const double *pin = nullptr, double *pout = nullptr) {
   Stage32Args a = base_args32(s);
   a.fs = fs;
   a.fn = s->g_fn;
@@ -493,6 +499,8 @@ int run_stage32(dgbgk_solver *s, int stage, const float *fs, float *out, double 
   a.out = out;
   a.stage = stage;
   a.rhow_out = rhow_out;
+  a.pin = pin;
+  a.pout = pout;
   double ca, co;
   rk_coefficients(stage, dt, ca, co);
   a.c_acc = (float)ca;
@@ -508,7 +516,7 @@ int run_stage32(dgbgk_solver *s, int stage, const float *fs, float *out, double 
 int run_stage(dgbgk_solver *s, int stage, const void *fs_, void *out_, double dt,
               double *rhow_out = nullptr, const double *pin = nullptr, double *pout = nullptr) {
   if (is_fp32(s->prec))
-    return run_stage32(s, stage, (const float *)fs_, (float *)out_, dt, rhow_out);
+    return run_stage32(s, stage, (const float *)fs_, (float *)out_, dt, rhow_out, pin, pout);
   const double *fs = (const double *)fs_;
   double *out = (double *)out_;
   hipError_t e;
@@ -1005,7 +1013,9 @@ namespace {
 // One RK4 step.  Registers: f_n, acc, and two stage buffers A/B so that a
 // stage never overwrites the state its neighbours still read.
 bool uses_partials(const dgbgk_solver *s) {
-  if (s->prec != DGBGK_FP64 || !s->d_part[0]) return false;
+  if (!s->d_part[0]) return false;
+  if (is_fp32(s->prec))  // (16-byte rows: Q Np is a multiple of 4 at these orders)
+    return s->fused && s->E == 1 && handoff_moments(s->p) && ((int64_t)s->Q * s->Np) % 4 == 0;
   if (!s->fused) return s->ntiles <= kMaxPartialTiles;
   return s->E == 1 && !s->persistent && handoff_moments(s->p);
 }
@@ -1028,8 +1038,11 @@ void stage_partials(const dgbgk_solver *s, int stage, const double *&pin, double
 // others) where they are stale: after f_n was set from outside a step.
 int ensure_partials(dgbgk_solver *s) {
   if (!uses_partials(s) || s->part_valid) return DGBGK_OK;
-  hipError_t e = launch_moment_rows(s->d_fn, s->d_vel, (int)s->K, s->Np, s->Q,
-                                    s->fused ? 1 : s->ntiles, s->d_part[0], s->stream);
+  hipError_t e =
+      is_fp32(s->prec)
+          ? launch_moment_rows32(s->g_fn, s->d_vel, (int)s->K, s->Np, s->Q, s->d_part[0], s->stream)
+          : launch_moment_rows(s->d_fn, s->d_vel, (int)s->K, s->Np, s->Q, s->fused ? 1 : s->ntiles,
+                               s->d_part[0], s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "moment rows kernel");
   s->part_valid = true;
   return DGBGK_OK;
@@ -1299,6 +1312,7 @@ int dgbgk_fold(dgbgk_solver *s) {
   if (!s->have_state) return fail(s, DGBGK_ESTATE, "no state: call init or set_state first");
   hipError_t e = launch_ref_fold(s->d_fref, s->g_fn, (size_t)s->K * s->Np * s->Q, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "fold kernel");
+  s->part_valid = false;  // the correction is zero now
   return ref_refresh(s);
 }
 
@@ -2029,6 +2043,7 @@ int dgbgk_implicit_step_noalloc(dgbgk_solver *s, int32_t scheme, int64_t nsteps,
 struct dgbgk_batch {
   struct Class {
     int prec = DGBGK_FP64, p = 1, cw = 0, contract = 0, ref = 0, lds_bin = 0;
+    int ho = 0;  // FP32: one-element members that hand their moments between stages
     std::vector<int> members;  // indices into s
     std::vector<int2> items;   // (member index within the class, element block)
     size_t lds = 0;
@@ -2114,6 +2129,7 @@ void fill_descriptors(dgbgk_batch *b, const double *dt) {
           a.c_acc = (float)ca;
           a.c_out = (float)co;
           a.stream_nt = nt;
+          stage_partials(s, stage, a.pin, a.pout);
           std::memcpy(dst, &a, sizeof a);
         } else {
           StageArgs a = base_args(s);
@@ -2160,7 +2176,7 @@ int launch_class(dgbgk_batch *b, const dgbgk_batch::Class &c, int stage, hipStre
   const int2 *items = (const int2 *)(b->dev + c.off_items);
   hipError_t e;
   if (is_fp32(c.prec))
-    e = launch_batch_stage32(c.p, stage, c.cw, c.contract, c.ref, (const Stage32Args *)descs, items,
+    e = launch_batch_stage32(c.p, stage, c.cw, c.contract, c.ref, c.ho, (const Stage32Args *)descs, items,
                              (int)c.items.size(), c.lds, c.groups, st);
   else
     e = launch_batch_stage(c.p, stage, (const StageArgs *)descs, items, (int)c.items.size(), c.lds,
@@ -2295,6 +2311,7 @@ int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream
     const int cw = f32 ? (((int64_t)s->Q * s->Np) % 4 == 0 ? 4 : 1) : 0;
     const int contract = is_bf(s->prec) ? 1 : 0;
     const int ref = is_ref(s->prec) ? 1 : 0;
+    const int ho = f32 && uses_partials(s) ? 1 : 0;
     int bin = 0;
     while (bin < 3 && s->lds > bins[bin]) ++bin;
     const int prec_class = f32 ? DGBGK_FP32 : DGBGK_FP64;
@@ -2302,7 +2319,7 @@ int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream
     for (; k < b->cls.size(); ++k) {
       const auto &c = b->cls[k];
       if (c.prec == prec_class && c.p == s->p && c.cw == cw && c.contract == contract && c.ref == ref &&
-          c.lds_bin == bin)
+          c.ho == ho && c.lds_bin == bin)
         break;
     }
     if (k == b->cls.size()) {
@@ -2312,6 +2329,7 @@ int dgbgk_batch_create(dgbgk_solver *const *solvers, int32_t n, void *hip_stream
       c.cw = cw;
       c.contract = contract;
       c.ref = ref;
+      c.ho = ho;
       c.lds_bin = bin;
       b->cls.push_back(c);
     }

@@ -279,12 +279,174 @@ __device__ __forceinline__ void update32(const Stage32Args &a, const float *tile
   }
 }
 
+// Whether one-element blocks of order P hand their output's moments to the
+// next stage: with 16-byte accesses (4 nodes of one velocity row) each
+// thread's accesses stay on one column of 4 nodes, and the four wavefronts'
+// sums fit the partial-product area.
+template <int P>
+__host__ __device__ constexpr bool handoff32_order() {
+  constexpr int NP = (P + 1) * (P + 1);
+  return NP % 4 == 0 && 64 % (NP / 4) == 0 && NP <= 16;
+}
+
+static_assert(handoff32_order<1>() == handoff_moments(1) && handoff32_order<2>() == handoff_moments(2) &&
+                  handoff32_order<3>() == handoff_moments(3) && handoff32_order<4>() == handoff_moments(4) &&
+                  handoff32_order<5>() == handoff_moments(5) && handoff32_order<6>() == handoff_moments(6) &&
+                  handoff32_order<7>() == handoff_moments(7) && handoff32_order<8>() == handoff_moments(8),
+              "the host's choice of orders that hand over moments matches the kernel's");
+
+// Sum of a double over the lanes of each 16-lane row that are m, 2m, ... apart
+// (m = 1, 2, 4, 8): rotations within the row (DPP).
+template <int M>
+__device__ __forceinline__ double row_rotate_add(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+  const int rlo = __builtin_amdgcn_update_dpp(0, lo, 0x120 + M, 0xf, 0xf, false);
+  const int rhi = __builtin_amdgcn_update_dpp(0, hi, 0x120 + M, 0xf, 0xf, false);
+  const long long r = ((long long)rhi << 32) | (unsigned int)rlo;
+  return v + __builtin_bit_cast(double, r);
+}
+
+// Sum of v over the lanes of the wavefront congruent to this lane modulo G
+// (G = 1, 2, 4): rotations within 16-lane rows, then shuffles across rows.
+template <int G>
+__device__ __forceinline__ double lane_group_sum(double v) {
+  static_assert(G == 1 || G == 2 || G == 4, "lane groups of 1, 2 or 4");
+  if constexpr (G <= 1) v = row_rotate_add<1>(v);
+  if constexpr (G <= 2) v = row_rotate_add<2>(v);
+  v = row_rotate_add<4>(v);
+  v = row_rotate_add<8>(v);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+// Phase 4 of a one-element block (the accesses of update32, 16 bytes) that
+// also sums the moments of its output over the velocities per node, in FP64,
+// for the next stage: rows 0..2 of po (1, e_x, e_y) from each thread's column
+// of 4 nodes (reduced across the lanes of a wavefront, then across the
+// wavefronts in red, 4 x 7 x NP doubles).  WALL: the element has wall faces;
+// its outputs also go to the LDS tile, from which the outgoing normal speed
+// times the output is summed for the nodes of each wall face (rows 3..6).
+template <int P, int MODE, bool NT, bool REF, bool WALL>
+__device__ __forceinline__ void update32_handoff(const Stage32Args &a, float *tile, size_t boff, int nch,
+                                                 int tid, int nthr, const int *nbr, double *red,
+                                                 double *po) {
+  using Sh = Shape32<P>;
+  constexpr int N1 = Sh::N1, NP = Sh::NP, S = Sh::S;
+  constexpr int CPE = NP / 4;  // 16-byte accesses per velocity row
+  constexpr int U = 4;
+  const float cacc = a.c_acc, cout = a.c_out;
+  const float *xr = (MODE == 1 ? a.fs : a.fn) + boff;
+  float *accr = a.acc + boff;
+  float *outr = a.out + boff;
+  const float *rr = REF ? a.rref + boff : nullptr;
+  const int w = tid % CPE;  // nthr is a multiple of CPE: the column never changes
+  double sm[3][4];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sm[c][i] = 0.0;
+  for (int c0 = tid; c0 < nch; c0 += nthr * U) {
+    float4v x[U], y[U], rv[REF ? U : 1];
+    if constexpr (REF) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * nthr;
+        if (c < nch) rv[u] = ld_once32<NT, float4v>(rr + (size_t)c * 4);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * nthr;
+      if (c < nch) x[u] = ld_once32<NT, float4v>(xr + (size_t)c * 4);
+    }
+    if (MODE == 2 || MODE == 4) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * nthr;
+        if (c < nch) y[u] = ld_once32<NT, float4v>(accr + (size_t)c * 4);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * nthr;
+      if (c >= nch) continue;
+      const int q = c / CPE;
+      float4v o, an;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float kv = tile[q * S + 4 * w + i];
+        if constexpr (REF) kv += rv[u][i];
+        float ai = 0.0f;
+        const float yi = (MODE == 2 || MODE == 4) ? y[u][i] : 0.0f;
+        o[i] = rk32<MODE>(kv, x[u][i], yi, cacc, cout, ai);
+        an[i] = ai;
+        if (WALL) tile[q * S + 4 * w + i] = o[i];  // (the position this thread read)
+      }
+      *reinterpret_cast<float4v *>(outr + (size_t)c * 4) = o;
+      if (MODE == 1 || MODE == 2) st_once32<NT, float4v>(accr + (size_t)c * 4, an);
+      const double ex = a.vel[q], ey = a.vel[a.Q + q];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double ov = (double)o[i];
+        sm[0][i] += ov;
+        sm[1][i] += ex * ov;
+        sm[2][i] += ey * ov;
+      }
+    }
+  }
+  // lanes with the same column are congruent modulo CPE
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sm[cc][i] = lane_group_sum<CPE>(sm[cc][i]);
+  const int wave = tid >> 6, lane = tid & 63;
+  if (lane < CPE) {
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) red[(wave * 7 + cc) * NP + 4 * lane + i] = sm[cc][i];
+  }
+  __syncthreads();
+  if constexpr (WALL) {
+    // face node m of this thread, velocity rows tid / N1, + nthr / N1, ...
+    const int m = tid % N1;
+    const int nd[4] = {m, m * N1 + P, P * N1 + m, m * N1};  // bottom, right, top, left
+    double ws[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = tid / N1; q < a.Q; q += nthr / N1) {
+      const double ex = a.vel[q], ey = a.vel[a.Q + q];
+      const double wt[4] = {ey < 0.0 ? -ey : 0.0, ex > 0.0 ? ex : 0.0, ey > 0.0 ? ey : 0.0,
+                            ex < 0.0 ? -ex : 0.0};
+#pragma unroll
+      for (int fc = 0; fc < 4; ++fc)
+        if (nbr[fc] < 0) ws[fc] += wt[fc] * (double)tile[q * S + nd[fc]];
+    }
+#pragma unroll
+    for (int fc = 0; fc < 4; ++fc) ws[fc] = lane_group_sum<N1>(ws[fc]);
+    if (lane < N1) {
+#pragma unroll
+      for (int fc = 0; fc < 4; ++fc) red[(wave * 7 + 3 + fc) * NP + nd[fc]] = ws[fc];
+    }
+    __syncthreads();
+  }
+  constexpr int W = WALL ? 7 : 3;  // (rows 3..6 hold sums at the wall faces' nodes only)
+  if (tid < W * NP) {
+    const int cc = tid / NP, n = tid - cc * NP;
+    double v = 0.0;
+    for (int wv = 0; wv < (nthr >> 6); ++wv) v += red[(wv * 7 + cc) * NP + n];
+    po[cc * NP + n] = v;
+  }
+}
+
 // MODE: 0 writes L(f_s); 1 first RK4 stage; 2 second and third; 4 fourth.
 // CW: floats per global access (4 when Q Np is a multiple of 4, else 1).
 // BF: the volume term's contractions Dr g, Ds g on bf16 matrix cores.
 // EFIX: elements per work-group fixed at compile time (0: a.E at run time);
 // the one-element form drops the block's index arithmetic.
-template <int P, int MODE, int CW, bool BF, int EFIX = 0, bool REF = false>
+// HO: a one-element block that reads its input's moments (a.pin) and writes
+// its output's (a.pout), compiled without the matrix-core moment product.
+template <int P, int MODE, int CW, bool BF, int EFIX = 0, bool REF = false, bool HO = false>
 __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
   using Sh = Shape32<P>;
   constexpr int N1 = Sh::N1, NP = Sh::NP, NFP = Sh::NFP, S = Sh::S, NB = Sh::NB;
@@ -312,6 +474,25 @@ __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
   if (tid < E * 4) {
     const int e = tid >> 2, fc = tid & 3;
     nbr[tid] = e < Eb ? neighbour32(k0 + e, fc, a) : -1;
+  }
+
+  // one-element blocks of orders 1 and 3 read the moments of g_s handed over
+  // by the stage that wrote it (rows 3..6, the wall sums, only where the
+  // element has a wall face); the loads are issued before the tile's
+  static_assert(!HO || (CW == 4 && handoff32_order<P>()), "moment handover: orders 1 and 3, 16-byte rows");
+  constexpr bool pin1 = HO;  // (the host sets a.pin, a.pout and one element per block)
+  const bool we = HO && a.wall_mask != 0 &&
+                  (neighbour32(k0, 0, a) < 0 || neighbour32(k0, 1, a) < 0 ||
+                   neighbour32(k0, 2, a) < 0 || neighbour32(k0, 3, a) < 0);
+  double pv[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (pin1 && tid < NP) {
+    const double *pp = a.pin + (size_t)k0 * 7 * NP + tid;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pv[c] = pp[c * NP];
+    if (we) {
+#pragma unroll
+      for (int c = 3; c < 7; ++c) pv[c] = pp[c * NP];
+    }
   }
 
   // reference form: the reference moments of this thread's node are loaded
@@ -358,7 +539,7 @@ __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
     const int tasks = E * NB;
     const int ks = tasks >= 4 ? 1 : 4 / tasks;
     const int qper = ((Q + ks - 1) / ks + 3) / 4 * 4;
-    for (int pr = wave; pr < tasks * ks; pr += nthr >> 6) {
+    for (int pr = wave; !pin1 && pr < tasks * ks; pr += nthr >> 6) {
       const int t = pr / ks, sl = pr % ks;
       const int e = t / NB, nb = t % NB;
       const int node = nb * 16 + (lane & 15);
@@ -403,10 +584,15 @@ __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
         double sm[7];
 #pragma unroll
         for (int c = 0; c < 7; ++c) sm[c] = 0.0;
-        for (int sl = 0; sl < ks; ++sl) {
-          const double *pp = part + ((size_t)(t * ks + sl) * 7) * 16;
+        if (pin1) {
 #pragma unroll
-          for (int c = 0; c < 7; ++c) sm[c] += pp[c * 16 + col];
+          for (int c = 0; c < 7; ++c) sm[c] = pv[c];  // (one element: idx == tid < NP)
+        } else {
+          for (int sl = 0; sl < ks; ++sl) {
+            const double *pp = part + ((size_t)(t * ks + sl) * 7) * 16;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) sm[c] += pp[c * 16 + col];
+          }
         }
         float *m = mom + (e2 * NP + n2) * MS;
         if constexpr (REF) {
@@ -581,15 +767,29 @@ __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
   __syncthreads();
 
   // ---- 4. RK4 update, coalesced over the contiguous block -----------------------
+  if constexpr (HO && MODE != 0) {
+    {
+      // one-element blocks handing their output's moments to the next stage
+      double *po = a.pout + (size_t)k0 * 7 * NP;
+      if (a.stream_nt) {
+        if (we) update32_handoff<P, MODE, true, REF, true>(a, tile, boff, nch, tid, nthr, nbr, part, po);
+        else update32_handoff<P, MODE, true, REF, false>(a, tile, boff, nch, tid, nthr, nbr, part, po);
+      } else {
+        if (we) update32_handoff<P, MODE, false, REF, true>(a, tile, boff, nch, tid, nthr, nbr, part, po);
+        else update32_handoff<P, MODE, false, REF, false>(a, tile, boff, nch, tid, nthr, nbr, part, po);
+      }
+      return;
+    }
+  }
   if (a.stream_nt)
     update32<P, MODE, CW, true, REF>(a, tile, boff, nch, tid, nthr);
   else
     update32<P, MODE, CW, false, REF>(a, tile, boff, nch, tid, nthr);
 }
 
-template <int P, int MODE, int CW, bool BF, int EFIX, bool REF>
+template <int P, int MODE, int CW, bool BF, int EFIX, bool REF, bool HO = false>
 __global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) {
-  stage32_block<P, MODE, CW, BF, EFIX, REF>(
+  stage32_block<P, MODE, CW, BF, EFIX, REF, HO>(
       a, strip_block32(xcd_block32(blockIdx.x, a.nblk), a.nx, EFIX > 0 ? EFIX : a.E, a.nblk));
 }
 
@@ -598,7 +798,7 @@ __global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) 
 // a descriptor table in the constant address space (see batch_stage_kernel).
 typedef __attribute__((address_space(4))) const Stage32Args ConstStage32Args;
 
-template <int P, int MODE, int CW, bool BF, bool REF>
+template <int P, int MODE, int CW, bool BF, bool REF, bool HO>
 __global__ __launch_bounds__(kBlock32) void batch_stage32_kernel(const Stage32Args *descs,
                                                                   const int2 *items, int nitems) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -613,7 +813,7 @@ __global__ __launch_bounds__(kBlock32) void batch_stage32_kernel(const Stage32Ar
 #else
     const Stage32Args a = descs[inst];  // host pass: the body is never run on the host
 #endif
-    stage32_block<P, MODE, CW, BF, 0, REF>(a, blk);
+    stage32_block<P, MODE, CW, BF, HO ? 1 : 0, REF, HO>(a, blk);
     __syncthreads();  // LDS is reused by the next item
   }
 }
@@ -708,6 +908,30 @@ __global__ void to_ref_kernel(const double *src, const double *fref, float *g, s
   g[d] = (float)(src[(size_t)q * KNP + i] - fref[d]);
 }
 
+// out[(k 7 + c) Np + n] = sum_q W[q][c] g[k][q][n] in FP64, W = (1, e_x,
+// e_y, the outgoing normal speed at the bottom, right, top, left wall).
+__global__ __launch_bounds__(256) void moment_rows32_kernel(const float *g, const double *vel, int K,
+                                                            int Np, int Q, double *out) {
+  const size_t KNP = (size_t)K * Np;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= KNP) return;
+  const size_t k = i / Np, n = i % Np;
+  double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+  for (int q = 0; q < Q; ++q) {
+    const double v = (double)g[(k * Q + q) * Np + n];
+    const double cx = vel[q], cy = vel[Q + q];
+    s[0] += v;
+    s[1] += cx * v;
+    s[2] += cy * v;
+    s[3] += (cy < 0.0 ? -cy : 0.0) * v;
+    s[4] += (cx > 0.0 ? cx : 0.0) * v;
+    s[5] += (cy > 0.0 ? cy : 0.0) * v;
+    s[6] += (cx < 0.0 ? -cx : 0.0) * v;
+  }
+  for (int c = 0; c < 7; ++c) out[(k * 7 + c) * Np + n] = s[c];
+}
+
 __device__ inline double nan_max32(double a, double b) { return (b > a || b != b) ? b : a; }
 
 __global__ __launch_bounds__(256) void residual32_kernel(const float *k, const double *vel, size_t KNP,
@@ -738,78 +962,90 @@ __global__ __launch_bounds__(256) void residual32_kernel(const float *k, const d
   }
 }
 
-template <int P, int MODE, int CW, bool BF, bool REF>
+template <int P, int MODE, int CW, bool BF, bool REF, bool HO>
 hipError_t launch_batch32_pmcb(const Stage32Args *descs, const int2 *items, int nitems, size_t lds,
                                int groups, hipStream_t st) {
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)batch_stage32_kernel<P, MODE, CW, BF, REF>,
+    hipError_t e = hipFuncSetAttribute((const void *)batch_stage32_kernel<P, MODE, CW, BF, REF, HO>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((batch_stage32_kernel<P, MODE, CW, BF, REF>), dim3((unsigned)groups),
+  hipLaunchKernelGGL((batch_stage32_kernel<P, MODE, CW, BF, REF, HO>), dim3((unsigned)groups),
                      dim3(kBlock32), lds, st, descs, items, nitems);
   return hipGetLastError();
 }
 
-template <int P, int CW, bool BF, bool REF>
+template <int P, int CW, bool BF, bool REF, bool HO>
 hipError_t launch_batch32_pcb(int stage, const Stage32Args *descs, const int2 *items, int nitems,
                               size_t lds, int groups, hipStream_t st) {
   switch (stage) {
-    case 0: return launch_batch32_pmcb<P, 0, CW, BF, REF>(descs, items, nitems, lds, groups, st);
-    case 1: return launch_batch32_pmcb<P, 1, CW, BF, REF>(descs, items, nitems, lds, groups, st);
+    case 0: return launch_batch32_pmcb<P, 0, CW, BF, REF, HO>(descs, items, nitems, lds, groups, st);
+    case 1: return launch_batch32_pmcb<P, 1, CW, BF, REF, HO>(descs, items, nitems, lds, groups, st);
     case 2:
-    case 3: return launch_batch32_pmcb<P, 2, CW, BF, REF>(descs, items, nitems, lds, groups, st);
-    case 4: return launch_batch32_pmcb<P, 4, CW, BF, REF>(descs, items, nitems, lds, groups, st);
+    case 3: return launch_batch32_pmcb<P, 2, CW, BF, REF, HO>(descs, items, nitems, lds, groups, st);
+    case 4: return launch_batch32_pmcb<P, 4, CW, BF, REF, HO>(descs, items, nitems, lds, groups, st);
     default: return hipErrorInvalidValue;
   }
 }
 
+// ho: a class of one-element members that hand their moments between stages.
 template <int P, bool BF, bool REF>
-hipError_t launch_batch32_pb(int stage, int cw, const Stage32Args *descs, const int2 *items,
+hipError_t launch_batch32_pb(int stage, int cw, int ho, const Stage32Args *descs, const int2 *items,
                              int nitems, size_t lds, int groups, hipStream_t st) {
-  if (cw == 4) return launch_batch32_pcb<P, 4, BF, REF>(stage, descs, items, nitems, lds, groups, st);
-  return launch_batch32_pcb<P, 1, BF, REF>(stage, descs, items, nitems, lds, groups, st);
+  if (ho) {
+    if constexpr (handoff32_order<P>())
+      if (cw == 4) return launch_batch32_pcb<P, 4, BF, REF, true>(stage, descs, items, nitems, lds, groups, st);
+    return hipErrorInvalidValue;
+  }
+  if (cw == 4) return launch_batch32_pcb<P, 4, BF, REF, false>(stage, descs, items, nitems, lds, groups, st);
+  return launch_batch32_pcb<P, 1, BF, REF, false>(stage, descs, items, nitems, lds, groups, st);
 }
 
 // The reference form and the bf16 contractions are built for p <= 4.
 constexpr int kMaxRefP = 4;
 
 template <bool BF, bool REF>
-hipError_t launch_batch32_b(int p, int stage, int cw, const Stage32Args *descs, const int2 *items,
+hipError_t launch_batch32_b(int p, int stage, int cw, int ho, const Stage32Args *descs, const int2 *items,
                             int nitems, size_t lds, int groups, hipStream_t st) {
   switch (p) {
-    case 1: return launch_batch32_pb<1, BF, REF>(stage, cw, descs, items, nitems, lds, groups, st);
-    case 2: return launch_batch32_pb<2, BF, REF>(stage, cw, descs, items, nitems, lds, groups, st);
-    case 3: return launch_batch32_pb<3, BF, REF>(stage, cw, descs, items, nitems, lds, groups, st);
-    case 4: return launch_batch32_pb<4, BF, REF>(stage, cw, descs, items, nitems, lds, groups, st);
+    case 1: return launch_batch32_pb<1, BF, REF>(stage, cw, ho, descs, items, nitems, lds, groups, st);
+    case 2: return launch_batch32_pb<2, BF, REF>(stage, cw, ho, descs, items, nitems, lds, groups, st);
+    case 3: return launch_batch32_pb<3, BF, REF>(stage, cw, ho, descs, items, nitems, lds, groups, st);
+    case 4: return launch_batch32_pb<4, BF, REF>(stage, cw, ho, descs, items, nitems, lds, groups, st);
     default: break;
   }
   if constexpr (!BF && !REF) {
     switch (p) {
-      case 5: return launch_batch32_pb<5, false, false>(stage, cw, descs, items, nitems, lds, groups, st);
-      case 6: return launch_batch32_pb<6, false, false>(stage, cw, descs, items, nitems, lds, groups, st);
-      case 7: return launch_batch32_pb<7, false, false>(stage, cw, descs, items, nitems, lds, groups, st);
-      case 8: return launch_batch32_pb<8, false, false>(stage, cw, descs, items, nitems, lds, groups, st);
+      case 5: return launch_batch32_pb<5, false, false>(stage, cw, ho, descs, items, nitems, lds, groups, st);
+      case 6: return launch_batch32_pb<6, false, false>(stage, cw, ho, descs, items, nitems, lds, groups, st);
+      case 7: return launch_batch32_pb<7, false, false>(stage, cw, ho, descs, items, nitems, lds, groups, st);
+      case 8: return launch_batch32_pb<8, false, false>(stage, cw, ho, descs, items, nitems, lds, groups, st);
       default: break;
     }
   }
   return hipErrorInvalidValue;
 }
 
-template <int P, int MODE, int CW, bool BF, int EFIX, bool REF>
+template <int P, int MODE, int CW, bool BF, int EFIX, bool REF, bool HO = false>
 hipError_t launch32_pmcbe(const Stage32Args &a, size_t lds, hipStream_t st) {
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void *)stage32_kernel<P, MODE, CW, BF, EFIX, REF>,
+    hipError_t e = hipFuncSetAttribute((const void *)stage32_kernel<P, MODE, CW, BF, EFIX, REF, HO>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((stage32_kernel<P, MODE, CW, BF, EFIX, REF>), dim3((unsigned)a.nblk),
+  hipLaunchKernelGGL((stage32_kernel<P, MODE, CW, BF, EFIX, REF, HO>), dim3((unsigned)a.nblk),
                      dim3(kBlock32), lds, st, a);
   return hipGetLastError();
 }
 
 template <int P, int MODE, int CW, bool BF, bool REF>
 hipError_t launch32_pmcb(const Stage32Args &a, size_t lds, hipStream_t st) {
+  if constexpr (CW == 4 && handoff32_order<P>()) {
+    // one-element blocks that read their input's moments (and, in RK4 stages,
+    // write their output's): a kernel without the matrix-core moment product
+    if (a.E == 1 && a.pin && (MODE == 0 || a.pout))
+      return launch32_pmcbe<P, MODE, CW, BF, 1, REF, true>(a, lds, st);
+  }
   if constexpr (P <= 4)
     if (a.E == 1) return launch32_pmcbe<P, MODE, CW, BF, 1, REF>(a, lds, st);
   return launch32_pmcbe<P, MODE, CW, BF, 0, REF>(a, lds, st);
@@ -876,14 +1112,14 @@ bool ref_form_available(int p, int contract) {
   return p >= 1 && p <= kMaxRefP;
 }
 
-hipError_t launch_batch_stage32(int p, int stage, int cw, int contract, int ref,
+hipError_t launch_batch_stage32(int p, int stage, int cw, int contract, int ref, int ho,
                                 const Stage32Args *descs, const int2 *items, int nitems, size_t lds,
                                 int groups, hipStream_t st) {
   if (nitems <= 0 || groups <= 0) return hipSuccess;
-  if (contract && ref) return launch_batch32_b<true, true>(p, stage, cw, descs, items, nitems, lds, groups, st);
-  if (contract) return launch_batch32_b<true, false>(p, stage, cw, descs, items, nitems, lds, groups, st);
-  if (ref) return launch_batch32_b<false, true>(p, stage, cw, descs, items, nitems, lds, groups, st);
-  return launch_batch32_b<false, false>(p, stage, cw, descs, items, nitems, lds, groups, st);
+  if (contract && ref) return launch_batch32_b<true, true>(p, stage, cw, ho, descs, items, nitems, lds, groups, st);
+  if (contract) return launch_batch32_b<true, false>(p, stage, cw, ho, descs, items, nitems, lds, groups, st);
+  if (ref) return launch_batch32_b<false, true>(p, stage, cw, ho, descs, items, nitems, lds, groups, st);
+  return launch_batch32_b<false, false>(p, stage, cw, ho, descs, items, nitems, lds, groups, st);
 }
 
 hipError_t launch_stage32(int p, const Stage32Args &a, size_t lds, int contract, int ref,
@@ -947,6 +1183,14 @@ hipError_t launch_init_equilibrium32(float *g, const double *vel, int K, int Np,
   dim3 grid((unsigned)((KNP + 255) / 256), (unsigned)Q);
   hipLaunchKernelGGL(init_equilibrium32_kernel, grid, dim3(256), 0, st, g, vel, KNP, Np, Q, rho0,
                      ux0, uy0, theta, rho_ref);
+  return hipGetLastError();
+}
+
+hipError_t launch_moment_rows32(const float *g, const double *vel, int K, int Np, int Q, double *out,
+                                hipStream_t st) {
+  const size_t KNP = (size_t)K * Np;
+  hipLaunchKernelGGL(moment_rows32_kernel, dim3((unsigned)((KNP + 255) / 256)), dim3(256), 0, st, g,
+                     vel, K, Np, Q, out);
   return hipGetLastError();
 }
 

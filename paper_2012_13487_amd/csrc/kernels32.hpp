@@ -28,6 +28,11 @@ struct Stage32Args {
   // f_r per node ([3][K Np], FP64).  NULL otherwise.
   const float *rref;
   const double *mref;
+  // moments handed between stages (one-element blocks of orders 1 and 3): the
+  // input's seven moment sums per node ([K][7][Np], FP64, of g) and the
+  // output's, written by the update pass; NULL: the block reduces its own
+  const double *pin;
+  double *pout;
   float D1[kMaxN1 * kMaxN1];
   float lift_lo[kMaxN1], lift_hi[kMaxN1];
   float rx, sy, fsx, fsy;
@@ -63,8 +68,9 @@ hipError_t launch_stage32(int p, const Stage32Args &a, size_t lds_bytes, int con
 
 // Batched FP32 stage over problems of order p with the same access width cw
 // (4 when Q Np is a multiple of 4, else 1), contraction variant and form;
-// items and descs as for launch_batch_stage.
-hipError_t launch_batch_stage32(int p, int stage, int cw, int contract, int ref,
+// items and descs as for launch_batch_stage.  ho: every member has one
+// element per block and hands its moments between stages (a.pin, a.pout).
+hipError_t launch_batch_stage32(int p, int stage, int cw, int contract, int ref, int ho,
                                 const Stage32Args *descs, const int2 *items, int nitems,
                                 size_t lds_bytes, int groups, hipStream_t stream);
 
@@ -96,6 +102,13 @@ hipError_t launch_init_equilibrium32(float *g, const double *vel, int K, int Np,
 // rho, ux, uy of f = g + w rho_ref at every node (FP64 sums).
 hipError_t launch_moments32(const float *g, const double *vel, int K, int Np, int Q,
                             double rho_ref, double *rho, double *ux, double *uy, hipStream_t stream);
+
+// Moment rows of an FP32 state g (element-major): out[k][7][Np] = sum over
+// velocities of (1, e_x, e_y, outgoing normal speed at the bottom, right,
+// top, left wall) times g, in FP64: the input moments of the stages that read
+// them (a.pin).
+hipError_t launch_moment_rows32(const float *g, const double *vel, int K, int Np, int Q, double *out,
+                                hipStream_t stream);
 
 // Residual of a rate k (float, element-major), as launch_residual.
 hipError_t launch_residual32(const float *k, const double *vel, int K, int Np, int Q, double scale,

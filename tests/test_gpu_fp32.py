@@ -313,3 +313,89 @@ def test_fp32_against_fp64_gpu_after_2000_steps():
     er, eu = _moment_errors(res[1], res[0])
     _say(f"  err rho {er:.2e} u {eu:.2e}")
     assert er < TOL32 and eu < TOL32, (er, eu)
+
+
+HANDOFF32_CASES = [
+    ("cavity_9x7_p3_nc12", workloads.cavity(n=9, ny=7, p=3, m=12, lid=0.1, kn=0.5)),
+    ("couette_6x5_p3_gh4", workloads.couette(nx=6, ny=5, p=3, kn=0.7)),
+    ("cavity_7x6_p1_nc10", workloads.cavity(n=7, ny=6, p=1, m=10, lid=0.2, kn=1.5)),
+    ("cavity_1x1_p3_nc8", workloads.cavity(n=1, ny=1, p=3, m=8, lid=0.1)),  # four wall faces
+]
+
+
+@pytest.mark.parametrize("prec", [binding.FP32, binding.FP32_REF, binding.FP32_BF16MMA])
+@pytest.mark.parametrize("name,spec", HANDOFF32_CASES, ids=[c[0] for c in HANDOFF32_CASES])
+def test_fp32_moment_handoff_matches_oracle(oracle_mod, name, spec, prec):
+    """One-element blocks of orders 1 and 3 take the FP64 moments of their
+    input from the update pass of the stage before (a moment pass over g_n
+    first): steps, residuals between them, a state set again, and (reference
+    form) a fold, against the oracle."""
+    pname = {v: k for k, v in binding.PRECISIONS.items()}[prec]
+    _say(f"[gpu] FP32 moment handoff {name} {pname}")
+    tol = TOL_BF if prec == binding.FP32_BF16MMA else TOL32
+    g = binding.Solver.from_spec(spec, precision=prec)
+    o = oracle_mod.Oracle.from_spec(spec)
+    g.set_block_elements(1)
+    assert g.tiling()["elems_per_group"] == 1
+    f = workloads.perturbed_state(67, o.w, o.K, o.Np, amp=0.05)
+    dt = o.stable_dt(0.2)
+    for s_ in (g, o):
+        s_.set_state(f)
+    g.step(6, dt)
+    o.rk4(6, dt)
+    r, rc = o.residual()
+    assert rc == 0 and abs(g.residual() - r) < tol * r
+    if prec == binding.FP32_REF:
+        g.fold()
+    g.step(6, dt)
+    o.rk4(6, dt)
+    er, eu = _moment_errors(g.moments(), o.moments())
+    assert er < tol and eu < tol, (er, eu)
+    f2 = workloads.perturbed_state(71, o.w, o.K, o.Np, amp=0.05)
+    for s_ in (g, o):
+        s_.set_state(f2)
+    g.step(8, dt)
+    o.rk4(8, dt)
+    er, eu = _moment_errors(g.moments(), o.moments())
+    _say(f"  err rho {er:.2e} u {eu:.2e}")
+    assert er < tol and eu < tol, (er, eu)
+
+
+def test_fp32_moment_handoff_batch_matches_solo():
+    """FP32 and reference-form members with one-element blocks form their own
+    batch classes (kernels that hand the moments over): states and residuals
+    agree bit for bit with the same solvers stepped alone, across a graph
+    replay, solo steps of the members in between, and a fold."""
+    _say("[gpu] FP32 moment handoff in a batch")
+    specs = [(c[1], p) for c in HANDOFF32_CASES[:3]
+             for p in (binding.FP32, binding.FP32_REF)]
+    def make():
+        out = []
+        for i, (sp, prec) in enumerate(specs):
+            g = binding.Solver.from_spec(sp, precision=prec)
+            g.set_block_elements(1)
+            g.set_state(workloads.perturbed_state(73 + i, g.w, g.K, g.Np, amp=0.05))
+            out.append(g)
+        return out
+    bm, solo = make(), make()
+    dts = np.array([g.stable_dt(0.2) for g in bm])
+    b = binding.Batch(bm, graph=3)
+    b.step(7, dts)
+    for g, dt in zip(solo, dts):
+        g.step(7, dt)
+    rb = b.residuals()
+    for i, (x, y) in enumerate(zip(bm, solo)):
+        assert np.array_equal(x.get_state(), y.get_state()), i
+        assert rb[i] == y.residual(), i
+    for i, (x, y, dt) in enumerate(zip(bm, solo, dts)):
+        if specs[i][1] == binding.FP32_REF:
+            x.fold()
+            y.fold()
+        x.step(3, dt)
+        y.step(3, dt)
+    b.step(4, dts)
+    for g, dt in zip(solo, dts):
+        g.step(4, dt)
+    for i, (x, y) in enumerate(zip(bm, solo)):
+        assert np.array_equal(x.get_state(), y.get_state()), i
+    b.close()
