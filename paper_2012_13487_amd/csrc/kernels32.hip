@@ -335,7 +335,7 @@ __device__ __forceinline__ void update32_handoff(const Stage32Args &a, float *ti
   using Sh = Shape32<P>;
   constexpr int N1 = Sh::N1, NP = Sh::NP, S = Sh::S;
   constexpr int CPE = NP / 4;  // 16-byte accesses per velocity row
-  constexpr int U = 4;
+  constexpr int U = REF ? 2 : 1;  // (measured: 4 / 2 / 1 -> 59.1 / 57.7 / 57.0 us, reference form 78.1 / 74.0 / 75.1)
   const float cacc = a.c_acc, cout = a.c_out;
   const float *xr = (MODE == 1 ? a.fs : a.fn) + boff;
   float *accr = a.acc + boff;
