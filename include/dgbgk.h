@@ -269,14 +269,21 @@ int dgbgk_synchronize(dgbgk_solver *s);
  * velocities of a block of elements per work-group when the tile fits in LDS,
  * else velocity tiles); 1 and 3: force the all-velocity (fused) form with one
  * work-group per element block; 2: force velocity tiles of
- * velocities_per_tile (0 = largest that fits); 4: the fused form run by
- * persistent wave-specialised work-groups that each walk a run of blocks
- * (p <= 3, at most 256 velocity rows per block; DGBGK_EINVAL otherwise).  The
- * tiled form reduces the node moments in a separate pass.  get_tiling reports
- * *fused = 0 (velocity tiles), 1 (fused, one work-group per block) or 2
- * (fused, persistent), and the LDS bytes per work-group.  The fused forms
- * give bit-identical results; the tiled form agrees to rounding.  This exists
- * for testing and tuning. */
+ * velocities_per_tile (0 = automatic: the largest of Q, Q/2, Q/4, ... that
+ * fits, rounded up to a multiple of 64 where the tile count stays); 4: the
+ * fused form run by persistent wave-specialised work-groups that each walk a
+ * run of blocks (p <= 3, at most 256 velocity rows per block; DGBGK_EINVAL
+ * otherwise).  The tiled form (up to four tiles), and the fused form with one
+ * element per work-group at orders 1 and 3 (FP64 and FP32 storage), take the
+ * node moments of a stage's input from the update pass of the stage before;
+ * a separate pass reduces them once after the state was set (init,
+ * set_state, an implicit step, a fold), and in every stage with more than
+ * four tiles.  get_tiling reports *fused = 0 (velocity tiles), 1 (fused, one
+ * work-group per block) or 2 (fused, persistent), and the LDS bytes per
+ * work-group.  The fused forms give bit-identical results, except one
+ * element per work-group at orders 1 and 3 (moments handed over: another
+ * summation order); the tiled form agrees to rounding.  This exists for
+ * testing and tuning. */
 int dgbgk_set_tiling(dgbgk_solver *s, int32_t mode, int32_t velocities_per_tile);
 int dgbgk_get_tiling(const dgbgk_solver *s, int32_t *fused, int32_t *elems_per_group,
                      int32_t *velocities_per_tile, size_t *lds_bytes);
