@@ -60,18 +60,37 @@ __host__ __device__ inline LdsLayout lds_layout(int NP, int NFP, int S, int E, i
   return L;
 }
 
-// out / new accumulator of one RK4 stage from k = L(f_s):
-//   MODE 1: acc = f_s + dt/6 k, out = f_s + dt/2 k          (x = f_s)
-//   MODE 2: acc = acc + dt/3 k, out = f_n + c dt k, c = 1/2, 1  (x = f_n, y = acc)
-//   MODE 4: out = acc + dt/6 k                               (x = acc)
+// out / new accumulator of one stage of classical RK4 from k = L(f_s), with
+// the accumulator first written in the second stage (from f_1 - f_n = dt/2 k1,
+// so the first stage writes one register and the second reads f_1 again
+// instead of an accumulator):
+//   MODE 1 (stage 1): out = f_s + dt/2 k                          (x = f_s)
+//   MODE 3 (stage 2): acc = f_n + (f_s - f_n) / 3 + dt/3 k,
+//                     out = f_n + dt/2 k                          (x = f_n, y = f_s)
+//   MODE 2 (stage 3): acc = acc + dt/3 k, out = f_n + dt k        (x = f_n, y = acc)
+//   MODE 4 (stage 4): out = acc + dt/6 k                          (x = acc)
 //   MODE 0: out = k
 template <int MODE>
 __device__ inline double rk_one(double kv, double x, double y, double ca, double co, double &an) {
   if (MODE == 0) return kv;
-  if (MODE == 1) { an = x + ca * kv; return x + co * kv; }
+  if (MODE == 1) return x + co * kv;
+  if (MODE == 3) { an = x + (y - x) * (1.0 / 3.0) + ca * kv; return x + co * kv; }
   if (MODE == 2) { an = y + ca * kv; return x + co * kv; }
   return x + ca * kv;
 }
+
+// The update's operands for a stage MODE, as above: x, y (y read only where
+// rk_reads_y), and whether the accumulator is written.
+template <int MODE>
+__device__ __forceinline__ const double *rk_x(const StageArgs &a) {
+  return MODE == 1 ? a.fs : (MODE == 2 || MODE == 3) ? a.fn : a.acc;
+}
+template <int MODE>
+__device__ __forceinline__ const double *rk_y(const StageArgs &a) {
+  return MODE == 3 ? a.fs : a.acc;
+}
+__host__ __device__ constexpr bool rk_reads_y(int mode) { return mode == 2 || mode == 3; }
+__host__ __device__ constexpr bool rk_writes_acc(int mode) { return mode == 2 || mode == 3; }
 template <int MODE>
 __device__ inline void rk_update(double kv, double x, double y, double ca, double co, double &o,
                                  double &an) {
@@ -503,8 +522,9 @@ __device__ __forceinline__ void update_rows(const StageArgs &a, const double *ti
   using V = typename std::conditional<Sh::VEC, double2v, double>::type;
   const size_t QNP = (size_t)a.Q * NP;
   const double cacc = a.c_acc, cout = a.c_out;
-  // x: f_s (stage 1), f_n (stages 2, 3), acc (stage 4); y: acc (stages 2, 3)
-  const double *xr = (MODE == 1 ? a.fs : MODE == 2 ? a.fn : a.acc) + boff;
+  // x: f_s (stage 1), f_n (stages 2, 3), acc (stage 4); y: f_s (stage 2), acc (stage 3)
+  const double *xr = rk_x<MODE>(a) + boff;
+  const double *yr = rk_y<MODE>(a) + boff;
   double *accr = a.acc + boff;
   double *outr = a.out + boff;
   for (int c0 = tid; c0 < nch; c0 += nthr * U) {
@@ -526,10 +546,10 @@ __device__ __forceinline__ void update_rows(const StageArgs &a, const double *ti
       for (int u = 0; u < U; ++u)
         if (ok[u]) x[u] = ld_once<NT, V>(xr + go[u]);
     }
-    if (MODE == 2) {
+    if (rk_reads_y(MODE)) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (ok[u]) y[u] = ld_once<NT, V>(accr + go[u]);
+        if (ok[u]) y[u] = ld_once<NT, V>(yr + go[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -537,7 +557,7 @@ __device__ __forceinline__ void update_rows(const StageArgs &a, const double *ti
       V o, an;
       rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
       *reinterpret_cast<V *>(outr + go[u]) = o;
-      if (MODE == 1 || MODE == 2) st_once<NT, V>(accr + go[u], an);
+      if (rk_writes_acc(MODE)) st_once<NT, V>(accr + go[u], an);
     }
   }
 }
@@ -557,6 +577,7 @@ __device__ __forceinline__ void update_pass(const StageArgs &a, const double *ti
   using V = typename std::conditional<Sh::VEC, double2v, double>::type;
   const size_t QNP = (size_t)a.Q * NP;
   const double cacc = a.c_acc, cout = a.c_out;
+  const double *yr = rk_y<MODE>(a) + (accr - a.acc);  // (at the tile's offset)
   V kv[U], x[U], y[U];
   size_t go[U];
   bool ok[U];
@@ -575,10 +596,10 @@ __device__ __forceinline__ void update_pass(const StageArgs &a, const double *ti
     for (int u = 0; u < U; ++u)
       if (ok[u]) x[u] = ld_once<NT, V>(xr + go[u]);
   }
-  if (MODE == 2) {
+  if (rk_reads_y(MODE)) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (ok[u]) y[u] = ld_once<NT, V>(accr + go[u]);
+      if (ok[u]) y[u] = ld_once<NT, V>(yr + go[u]);
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -586,7 +607,7 @@ __device__ __forceinline__ void update_pass(const StageArgs &a, const double *ti
     V o, an;
     rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
     *reinterpret_cast<V *>(outr + go[u]) = o;
-    if (MODE == 1 || MODE == 2) st_once<NT, V>(accr + go[u], an);
+    if (rk_writes_acc(MODE)) st_once<NT, V>(accr + go[u], an);
     if (keep) {  // the output replaces L(f) at the same LDS position (this thread's own)
       const int c = c0 + u * nthr;
       int q, e, w;
@@ -614,6 +635,7 @@ __device__ __forceinline__ void update_columns(const StageArgs &a, double *tile,
   const int G = nthr / NP;
   const int g = tid / NP, n = tid - g * NP;
   const double cacc = a.c_acc, cout = a.c_out;
+  const double *yr = rk_y<MODE>(a) + (accr - a.acc);  // (at the tile's offset)
   double sm[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (g < G) {
     for (int qa = g; qa < Qb; qa += G * U) {
@@ -634,11 +656,11 @@ __device__ __forceinline__ void update_columns(const StageArgs &a, double *tile,
           if (q < Qb) x[u] = ld_once<NT, double>(xr + (size_t)q * NP + n);
         }
       }
-      if (MODE == 2) {
+      if (rk_reads_y(MODE)) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int q = qa + u * G;
-          if (q < Qb) y[u] = ld_once<NT, double>(accr + (size_t)q * NP + n);
+          if (q < Qb) y[u] = ld_once<NT, double>(yr + (size_t)q * NP + n);
         }
       }
 #pragma unroll
@@ -648,7 +670,7 @@ __device__ __forceinline__ void update_columns(const StageArgs &a, double *tile,
         double o, an = 0.0;
         rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
         outr[(size_t)q * NP + n] = o;
-        if (MODE == 1 || MODE == 2) st_once<NT, double>(accr + (size_t)q * NP + n, an);
+        if (rk_writes_acc(MODE)) st_once<NT, double>(accr + (size_t)q * NP + n, an);
         const double ex = cx[u], ey = cy[u];
         sm[0] += o;
         sm[1] += ex * o;
@@ -707,7 +729,8 @@ __device__ __forceinline__ void update_rows_handoff(const StageArgs &a, const do
   constexpr int W = WALL ? 7 : 3;
   using V = typename std::conditional<Sh::VEC, double2v, double>::type;
   const double cacc = a.c_acc, cout = a.c_out;
-  const double *xr = (MODE == 1 ? a.fs : MODE == 2 ? a.fn : a.acc) + boff;
+  const double *xr = rk_x<MODE>(a) + boff;
+  const double *yr = rk_y<MODE>(a) + boff;
   double *accr = a.acc + boff;
   double *outr = a.out + boff;
   const int w = tid % CPE;  // nthr is a multiple of CPE: the column never changes
@@ -735,15 +758,15 @@ __device__ __forceinline__ void update_rows_handoff(const StageArgs &a, const do
         ey[u] = a.vel[a.Q + q];
       }
     }
-    if (MODE == 1 || MODE == 2 || MODE == 4) {
+    if (MODE != 0) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (ok[u]) x[u] = ld_once<NT, V>(xr + go[u]);
     }
-    if (MODE == 2) {
+    if (rk_reads_y(MODE)) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (ok[u]) y[u] = ld_once<NT, V>(accr + go[u]);
+        if (ok[u]) y[u] = ld_once<NT, V>(yr + go[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -751,7 +774,7 @@ __device__ __forceinline__ void update_rows_handoff(const StageArgs &a, const do
       V o, an;
       rk_update<MODE>(kv[u], x[u], y[u], cacc, cout, o, an);
       *reinterpret_cast<V *>(outr + go[u]) = o;
-      if (MODE == 1 || MODE == 2) st_once<NT, V>(accr + go[u], an);
+      if (rk_writes_acc(MODE)) st_once<NT, V>(accr + go[u], an);
       const double *ov = reinterpret_cast<const double *>(&o);
       double wt[W];
       wt[0] = 1.0;
@@ -792,7 +815,7 @@ __device__ __forceinline__ void update_rows_handoff(const StageArgs &a, const do
   }
 }
 
-// MODE: 0 writes L(f_s); 1 first RK4 stage; 2 second and third; 4 fourth.
+// MODE: 0 writes L(f_s); 1 first RK4 stage; 3 second; 2 third; 4 fourth (see rk_one).
 // FUSED: the block reduces its own moments and wall densities (a.fused).
 // One element block blk and velocity tile tile_y of the stage, by one
 // work-group; the body of the general kernel and of the batched kernel.
@@ -974,7 +997,7 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
 
   // ---- 4. RK4 register update, coalesced over each velocity row -----------------
   if constexpr (NTM != 0) {
-    const double *xr = (MODE == 1 ? a.fs : MODE == 2 ? a.fn : a.acc) + boff;
+    const double *xr = rk_x<MODE>(a) + boff;
     double *accr = a.acc + boff;
     double *outr = a.out + boff;
     if (MODE != 0 && a.pout && E == 1 && 7 * (nthr / NP) * NP <= Qb * S) {
@@ -1124,8 +1147,8 @@ __device__ __forceinline__ void pipe_issue(const StageArgs &a, int t, int first,
   if (MODE != 0 && t >= 2 && t - 2 < nb) {
     const int bu = first + (t - 2) * nl, Ebu = min(E, a.K - bu * E);
     const size_t boff = (size_t)bu * E * QNP;
-    const double *xr = (MODE == 1 ? a.fs : MODE == 2 ? a.fn : a.acc) + boff;
-    const double *yr = a.acc + boff;
+    const double *xr = rk_x<MODE>(a) + boff;
+    const double *yr = rk_y<MODE>(a) + boff;
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const int c = tid + u * kBlock;
@@ -1134,7 +1157,7 @@ __device__ __forceinline__ void pipe_issue(const StageArgs &a, int t, int first,
       if (c < nch && e < Ebu) {
         const uint32_t go = (uint32_t)e * QNP + (uint32_t)(q * NP + CW * w);
         x[u] = ld32<V>(xr, go);
-        if (MODE == 2) y[u] = ld32<V>(yr, go);
+        if (rk_reads_y(MODE)) y[u] = ld32<V>(yr, go);
       }
     }
   }
@@ -1264,7 +1287,7 @@ __global__ __launch_bounds__(2 * kBlock) void pipe_kernel(const StageArgs a) {
             V o, an;
             rk_update<MODE>(kv, x[u], y[u], a.c_acc, a.c_out, o, an);
             st32<V>(a.out + boff, go, o);
-            if (MODE == 1 || MODE == 2) st32<V>(a.acc + boff, go, an);
+            if (rk_writes_acc(MODE)) st32<V>(a.acc + boff, go, an);
           }
         }
       }
@@ -1461,7 +1484,7 @@ hipError_t launch_stream_p(const StageArgs &a, size_t lds, int groups, hipStream
   switch (a.stage) {
     case 0: return launch_stream_pm<P, 0>(a, lds, groups, st);
     case 1: return launch_stream_pm<P, 1>(a, lds, groups, st);
-    case 2:
+    case 2: return launch_stream_pm<P, 3>(a, lds, groups, st);
     case 3: return launch_stream_pm<P, 2>(a, lds, groups, st);
     case 4: return launch_stream_pm<P, 4>(a, lds, groups, st);
     default: return hipErrorInvalidValue;
@@ -1487,7 +1510,7 @@ hipError_t launch_batch_p(int stage, const StageArgs *descs, const int2 *items, 
   switch (stage) {
     case 0: return launch_batch_pm<P, 0>(descs, items, nitems, lds, groups, st);
     case 1: return launch_batch_pm<P, 1>(descs, items, nitems, lds, groups, st);
-    case 2:
+    case 2: return launch_batch_pm<P, 3>(descs, items, nitems, lds, groups, st);
     case 3: return launch_batch_pm<P, 2>(descs, items, nitems, lds, groups, st);
     case 4: return launch_batch_pm<P, 4>(descs, items, nitems, lds, groups, st);
     default: return hipErrorInvalidValue;
@@ -1499,7 +1522,7 @@ hipError_t launch_stage_p(const StageArgs &a, size_t lds, int ntiles, hipStream_
   switch (a.stage) {
     case 0: return launch_stage_pm<P, 0>(a, lds, ntiles, st);
     case 1: return launch_stage_pm<P, 1>(a, lds, ntiles, st);
-    case 2:
+    case 2: return launch_stage_pm<P, 3>(a, lds, ntiles, st);
     case 3: return launch_stage_pm<P, 2>(a, lds, ntiles, st);
     case 4: return launch_stage_pm<P, 4>(a, lds, ntiles, st);
     default: return hipErrorInvalidValue;
