@@ -64,7 +64,8 @@ __host__ __device__ inline LdsLayout lds_layout(int NP, int NFP, int S, int E, i
 // the accumulator first written in the second stage (from f_1 - f_n = dt/2 k1,
 // so the first stage writes one register and the second reads f_1 again
 // instead of an accumulator):
-//   MODE 1 (stage 1): out = f_s + dt/2 k                          (x = f_s)
+//   MODE 1 (stage 1): out = f_s + dt/2 k, formed by the row phase (row_rhs), which
+//                     holds f_s and k; the update stores it
 //   MODE 3 (stage 2): acc = f_n + (f_s - f_n) / 3 + dt/3 k,
 //                     out = f_n + dt/2 k                          (x = f_n, y = f_s)
 //   MODE 2 (stage 3): acc = acc + dt/3 k, out = f_n + dt k        (x = f_n, y = acc)
@@ -73,7 +74,7 @@ __host__ __device__ inline LdsLayout lds_layout(int NP, int NFP, int S, int E, i
 template <int MODE>
 __device__ inline double rk_one(double kv, double x, double y, double ca, double co, double &an) {
   if (MODE == 0) return kv;
-  if (MODE == 1) return x + co * kv;
+  if (MODE == 1) return kv;
   if (MODE == 3) { an = x + (y - x) * (1.0 / 3.0) + ca * kv; return x + co * kv; }
   if (MODE == 2) { an = y + ca * kv; return x + co * kv; }
   return x + ca * kv;
@@ -89,6 +90,7 @@ template <int MODE>
 __device__ __forceinline__ const double *rk_y(const StageArgs &a) {
   return MODE == 3 ? a.fs : a.acc;
 }
+__host__ __device__ constexpr bool rk_reads_x(int mode) { return mode == 2 || mode == 3 || mode == 4; }
 __host__ __device__ constexpr bool rk_reads_y(int mode) { return mode == 2 || mode == 3; }
 __host__ __device__ constexpr bool rk_writes_acc(int mode) { return mode == 2 || mode == 3; }
 template <int MODE>
@@ -414,7 +416,7 @@ __device__ __forceinline__ RowVel row_vel(const StageArgs &a, int qg) {
   return v;
 }
 
-template <int P>
+template <int P, int MODE = 0>
 __device__ __forceinline__ void row_rhs(const StageArgs &a, double *row, const double *mm,
                                         const double *rwe, const RowVel &rv, int nbx, int nby,
                                         const double (&px)[P + 1], const double (&py)[P + 1]) {
@@ -481,6 +483,10 @@ __device__ __forceinline__ void row_rhs(const StageArgs &a, double *row, const d
     const double feq = wq * m4[2] * (m4[3] + eu * (a.theta_inv + eu * a.half_theta2_inv));
     kk[nn] += (feq - f[nn]) * a.inv_tau;
   }
+  if constexpr (MODE == 1) {  // the first RK4 stage's output, f_s + dt/2 L(f_s)
+#pragma unroll
+    for (int c = 0; c < NP; ++c) kk[c] = f[c] + a.c_out * kk[c];
+  }
   if (Sh::VEC) {
 #pragma unroll
     for (int c = 0; c < NP / 2; ++c)
@@ -541,7 +547,7 @@ __device__ __forceinline__ void update_rows(const StageArgs &a, const double *ti
       go[u] = e * QNP + q * NP + CW * w;
       if (ok[u]) kv[u] = lds_get<V>(tile + (q * E + e) * S + CW * w);
     }
-    if (MODE != 0) {
+    if (rk_reads_x(MODE)) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (ok[u]) x[u] = ld_once<NT, V>(xr + go[u]);
@@ -591,7 +597,7 @@ __device__ __forceinline__ void update_pass(const StageArgs &a, const double *ti
     go[u] = e * QNP + q * NP + CW * w;
     if (ok[u]) kv[u] = lds_get<V>(tile + (q * E + e) * S + CW * w);
   }
-  if (MODE != 0) {
+  if (rk_reads_x(MODE)) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (ok[u]) x[u] = ld_once<NT, V>(xr + go[u]);
@@ -649,7 +655,7 @@ __device__ __forceinline__ void update_columns(const StageArgs &a, double *tile,
           cy[u] = a.vel[a.Q + q0 + q];
         }
       }
-      if (MODE != 0) {
+      if (rk_reads_x(MODE)) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int q = qa + u * G;
@@ -758,7 +764,7 @@ __device__ __forceinline__ void update_rows_handoff(const StageArgs &a, const do
         ey[u] = a.vel[a.Q + q];
       }
     }
-    if (MODE != 0) {
+    if (rk_reads_x(MODE)) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (ok[u]) x[u] = ld_once<NT, V>(xr + go[u]);
@@ -991,7 +997,7 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
     const int nbx = nbr[e * 4 + (rv.cx > 0.0 ? 3 : 1)], nby = nbr[e * 4 + (rv.cy > 0.0 ? 0 : 2)];
     double px[NFP], py[NFP];
     row_traces<P>(a, qg, k0 + e, nbx, nby, px, py);
-    row_rhs<P>(a, tile + r * S, mom + e * NP * 4, rw + e * 4 * NFP, rv, nbx, nby, px, py);
+    row_rhs<P, MODE>(a, tile + r * S, mom + e * NP * 4, rw + e * 4 * NFP, rv, nbx, nby, px, py);
   }
   __syncthreads();
 
@@ -1144,7 +1150,7 @@ __device__ __forceinline__ void pipe_issue(const StageArgs &a, int t, int first,
       row_traces32<P>(a, cx, cy, rq, nbx, nby, px, py);
     }
   }
-  if (MODE != 0 && t >= 2 && t - 2 < nb) {
+  if (rk_reads_x(MODE) && t >= 2 && t - 2 < nb) {
     const int bu = first + (t - 2) * nl, Ebu = min(E, a.K - bu * E);
     const size_t boff = (size_t)bu * E * QNP;
     const double *xr = rk_x<MODE>(a) + boff;
@@ -1302,7 +1308,7 @@ __global__ __launch_bounds__(2 * kBlock) void pipe_kernel(const StageArgs a) {
         qx[m] = tr[m];
         qy[m] = tr[NFP + m];
       }
-      row_rhs<P>(a, tile_c + tid * S, mom + re * NP * 4, rw + re * 4 * NFP, rv, nbx, nby, qx, qy);
+      row_rhs<P, MODE>(a, tile_c + tid * S, mom + re * NP * 4, rw + re * 4 * NFP, rv, nbx, nby, qx, qy);
     }
     __syncthreads();
   }
