@@ -61,23 +61,22 @@ __host__ __device__ inline LdsLayout lds_layout(int NP, int NFP, int S, int E, i
 }
 
 // out / new accumulator of one stage of classical RK4 from k = L(f_s), with
-// the accumulator first written in the second stage (from f_1 - f_n = dt/2 k1,
-// so the first stage writes one register and the second reads f_1 again
-// instead of an accumulator):
-//   MODE 1 (stage 1): out = f_s + dt/2 k, formed by the row phase (row_rhs), which
-//                     holds f_s and k; the update stores it
+// the accumulator written once per step, in the second stage (f_1 - f_n =
+// dt/2 k1 and f_3 - f_n = dt k3 stand for the first and third rates), so that
+// stages 1 and 3 move no accumulator; where the row phase holds f_s and k it
+// forms the stage's share itself (row_rhs), and kv is that value:
+//   MODE 1 (stage 1): out = kv = f_s + dt/2 k
 //   MODE 3 (stage 2): acc = f_n + (f_s - f_n) / 3 + dt/3 k,
 //                     out = f_n + dt/2 k                          (x = f_n, y = f_s)
-//   MODE 2 (stage 3): acc = acc + dt/3 k, out = f_n + dt k        (x = f_n, y = acc)
-//   MODE 4 (stage 4): out = acc + dt/6 k                          (x = acc)
+//   MODE 2 (stage 3): out = f_n + dt k                            (x = f_n)
+//   MODE 4 (stage 4): out = acc - f_n / 3 + kv, kv = f_s / 3 + dt/6 k  (x = acc, y = f_n)
 //   MODE 0: out = k
 template <int MODE>
 __device__ inline double rk_one(double kv, double x, double y, double ca, double co, double &an) {
-  if (MODE == 0) return kv;
-  if (MODE == 1) return kv;
+  if (MODE == 0 || MODE == 1) return kv;
   if (MODE == 3) { an = x + (y - x) * (1.0 / 3.0) + ca * kv; return x + co * kv; }
-  if (MODE == 2) { an = y + ca * kv; return x + co * kv; }
-  return x + ca * kv;
+  if (MODE == 2) return x + co * kv;
+  return x - y * (1.0 / 3.0) + kv;
 }
 
 // The update's operands for a stage MODE, as above: x, y (y read only where
@@ -88,11 +87,11 @@ __device__ __forceinline__ const double *rk_x(const StageArgs &a) {
 }
 template <int MODE>
 __device__ __forceinline__ const double *rk_y(const StageArgs &a) {
-  return MODE == 3 ? a.fs : a.acc;
+  return MODE == 3 ? a.fs : a.fn;
 }
 __host__ __device__ constexpr bool rk_reads_x(int mode) { return mode == 2 || mode == 3 || mode == 4; }
-__host__ __device__ constexpr bool rk_reads_y(int mode) { return mode == 2 || mode == 3; }
-__host__ __device__ constexpr bool rk_writes_acc(int mode) { return mode == 2 || mode == 3; }
+__host__ __device__ constexpr bool rk_reads_y(int mode) { return mode == 3 || mode == 4; }
+__host__ __device__ constexpr bool rk_writes_acc(int mode) { return mode == 3; }
 template <int MODE>
 __device__ inline void rk_update(double kv, double x, double y, double ca, double co, double &o,
                                  double &an) {
@@ -486,6 +485,9 @@ __device__ __forceinline__ void row_rhs(const StageArgs &a, double *row, const d
   if constexpr (MODE == 1) {  // the first RK4 stage's output, f_s + dt/2 L(f_s)
 #pragma unroll
     for (int c = 0; c < NP; ++c) kk[c] = f[c] + a.c_out * kk[c];
+  } else if constexpr (MODE == 4) {  // the last stage's share, f_3 / 3 + dt/6 L(f_3)
+#pragma unroll
+    for (int c = 0; c < NP; ++c) kk[c] = f[c] * (1.0 / 3.0) + a.c_acc * kk[c];
   }
   if (Sh::VEC) {
 #pragma unroll
@@ -528,7 +530,7 @@ __device__ __forceinline__ void update_rows(const StageArgs &a, const double *ti
   using V = typename std::conditional<Sh::VEC, double2v, double>::type;
   const size_t QNP = (size_t)a.Q * NP;
   const double cacc = a.c_acc, cout = a.c_out;
-  // x: f_s (stage 1), f_n (stages 2, 3), acc (stage 4); y: f_s (stage 2), acc (stage 3)
+  // x: f_n (stages 2, 3), acc (stage 4); y: f_s (stage 2), f_n (stage 4)
   const double *xr = rk_x<MODE>(a) + boff;
   const double *yr = rk_y<MODE>(a) + boff;
   double *accr = a.acc + boff;
