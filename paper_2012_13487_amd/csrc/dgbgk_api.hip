@@ -51,14 +51,14 @@ bool is_bf(int precision) { return precision == DGBGK_FP32_BF16MMA || precision 
 bool is_ref(int precision) { return precision == DGBGK_FP32_REF || precision == DGBGK_FP32_BF16MMA_REF; }
 bool valid_precision(int precision) { return precision == DGBGK_FP64 || is_fp32(precision); }
 
-// State registers (FP64, or the FP32 deviation), an FP64 transfer buffer for
-// the FP32 precisions, then the small tables.
 // Velocity tiles whose moment partials a state of this precision keeps.
 int part_tiles(int precision, int Np) {
   if (precision == DGBGK_FP64) return kMaxPartialTiles;
   return (Np == 4 || Np == 16) ? 1 : 0;  // the orders that hand moments over (1 and 3)
 }
 
+// State registers (FP64, or the FP32 deviation), an FP64 transfer buffer for
+// the FP32 precisions, then the small tables.
 Layout make_layout(int64_t K, int Np, int Nfp, int Q, int precision) {
   Layout L{};
   const size_t ndof = (size_t)K * Np * Q;
@@ -1017,8 +1017,7 @@ int dgbgk_state_device_ptr(dgbgk_solver *s, void **ptr) {
 
 namespace {
 
-// One RK4 step.  Registers: f_n, acc, and two stage buffers A/B so that a
-// stage never overwrites the state its neighbours still read.
+// Whether the stages hand moment partials to the next (see stage_partials).
 bool uses_partials(const dgbgk_solver *s) {
   if (!s->d_part[0]) return false;
   if (is_fp32(s->prec))  // (16-byte rows: Q Np is a multiple of 4 at these orders)
@@ -1055,6 +1054,8 @@ int ensure_partials(dgbgk_solver *s) {
   return DGBGK_OK;
 }
 
+// One RK4 step.  Registers: f_n, acc, and two stage buffers A/B so that a
+// stage never overwrites the state its neighbours still read.
 int enqueue_rk4_step(dgbgk_solver *s, double dt) {
   int rc;
   void *fn = s->d_fn, *A = s->d_a, *B = s->d_b;
