@@ -67,6 +67,12 @@ def test_tiling_choice():
     big = binding.Solver.from_spec(workloads.CAVITY_128x128_P4_NC24_KN8)
     t = big.tiling()
     assert not t["fused"] and t["lds_bytes"] <= 80 * 1024
+    # 576 velocities: two tiles (halving gives 288), rounded up to whole 64-row
+    # wavefronts: 320 + 256
+    assert t["velocities_per_tile"] == 320
+    # 4096 velocities at p = 2: halved to 1024 (74 KB of LDS), already whole wavefronts
+    huge_q = binding.Solver.from_spec(workloads.cavity(n=2, p=2, m=64, lid=0.1))
+    assert huge_q.tiling()["velocities_per_tile"] == 1024 and not huge_q.tiling()["fused"]
     s.set_tiling(2, 48)
     assert s.tiling() == {"fused": False, "persistent": False, "elems_per_group": 1,
                           "velocities_per_tile": 48, "lds_bytes": s.tiling()["lds_bytes"]}
