@@ -581,7 +581,7 @@ __device__ __forceinline__ void update_pass(const StageArgs &a, const double *ti
   constexpr int NP = Sh::NP, S = Sh::S;
   constexpr int CW = Sh::VEC ? 2 : 1;
   constexpr int CPE = NP / CW;
-  constexpr int U = 16;
+  constexpr int U = Sh::VEC ? 8 : 16;  // (as stage_block: its pass loop steps by this)
   using V = typename std::conditional<Sh::VEC, double2v, double>::type;
   const size_t QNP = (size_t)a.Q * NP;
   const double cacc = a.c_acc, cout = a.c_out;
@@ -838,7 +838,7 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
   constexpr int CPE = NP / CW;         // accesses per element per velocity
   // global accesses in flight per thread (measured: 8 for fused blocks,
   // 16 for velocity tiles: 2850 -> 2640 us on the 128x128 p = 4 cavity)
-  constexpr int U = FUSED ? 8 : 16;
+  constexpr int U = (FUSED || Sh::VEC) ? 8 : 16;
   using V = typename std::conditional<Sh::VEC, double2v, double>::type;
   extern __shared__ double lds[];
   const int E = EFIX > 0 ? EFIX : a.E, log2E = EFIX == 1 ? 0 : a.log2E;
