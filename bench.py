@@ -32,6 +32,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 ALG_BYTES_PER_DOF_STAGE = 32.0  # FP64 RK4, 3 registers: 24/40/40/24 B per stage -> 32 mean
+# what the FP64 kernels move (the accumulator written once per step): 16/32/24/32 -> 26 mean
+ALG_BYTES_PER_DOF_STAGE_KERNEL = 26.0
 # FP32 increment-form RK4: 12/20/20/16 B per stage -> 17 mean (what the
 # kernels move); the method's own FP32 figure (3 registers) is 16 B
 ALG_BYTES_PER_DOF_STAGE_FP32 = 17.0
@@ -600,6 +602,9 @@ def main():
             "kernel": "stage_kernel<3>",
             "avg_launch_us": stage_us,
             "alg_bytes_per_launch": ALG_BYTES_PER_DOF_STAGE * dof,
+            "kernel_alg_bytes_per_launch": ALG_BYTES_PER_DOF_STAGE_KERNEL * dof,
+            "frac_at_kernel_bytes": ALG_BYTES_PER_DOF_STAGE_KERNEL * dof / (stage_us * 1e-6) / 1e9
+                                    / HBM_PEAK_GBS,
         },
         "cpu_baseline": None,
     }
