@@ -399,3 +399,25 @@ def test_fp32_moment_handoff_batch_matches_solo():
     for i, (x, y) in enumerate(zip(bm, solo)):
         assert np.array_equal(x.get_state(), y.get_state()), i
     b.close()
+
+
+def test_moment_handoff_streaming_hints_against_fp64_gpu():
+    """A cavity large enough (96x96 p=3 NC 16x16, 604 MB per FP32 state set)
+    that the FP32 and reference-form stages move their once-read streams with
+    non-temporal hints, in the one-element blocks that hand their moments on:
+    50 RK4 steps of a perturbed state against the FP64 GPU path (itself held
+    to the oracle at 1e-12), at the FP32 bar."""
+    _say("[gpu] moment handoff with streaming hints: 96x96 p3 nc16 vs FP64 GPU")
+    spec = workloads.cavity(n=96, p=3, m=16, lid=0.1)
+    res = {}
+    for prec in (binding.FP64, binding.FP32, binding.FP32_REF):
+        g = binding.Solver.from_spec(spec, precision=prec, stream="torch", torch_memory=True)
+        assert g.tiling()["fused"] and g.tiling()["elems_per_group"] == 1
+        g.set_state(workloads.perturbed_state(79, g.w, g.K, g.Np, amp=0.05))
+        g.step(50, g.stable_dt(spec.cfl))
+        res[prec] = g.moments()
+        g.close()
+    for prec in (binding.FP32, binding.FP32_REF):
+        er, eu = _moment_errors(res[prec], res[binding.FP64])
+        _say(f"  precision {prec}: err rho {er:.2e} u {eu:.2e}")
+        assert er < TOL32 and eu < TOL32, (prec, er, eu)
