@@ -1064,7 +1064,14 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
 // One work-group per (element block, velocity tile); the general kernel.
 // FK: 0 velocity-tiled blocks, 1 fused blocks, 2 fused blocks of one element.
 template <int P, int MODE, int FK>
-__global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
+// Fused blocks of orders 1-3 ask for three resident wavefronts per SIMD: the
+// compiler then keeps the moment product's accumulators in ordinary VGPRs
+// (168 at most, no spills) instead of 32 extra accumulation registers, which
+// had capped these kernels at two (measured: 256x256 p = 2 Couette, 16
+// elements per block, 199 -> 157 us per stage; 128x128 p = 2 NC 16x16, one
+// element, 448 -> 380 us).
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((FK >= 1 && P <= 3) ? 3 : 1)))
+void stage_kernel(const StageArgs a) {
   const int blk = strip_block(xcd_block(blockIdx.x, a.nblk), a.nx, a.log2E, a.nblk);
   // Code layouts chosen by measurement: the fused block with the run-time
   // cache policy, the velocity-tiled block with one copy per policy.
@@ -1088,8 +1095,10 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageArgs a) {
 typedef __attribute__((address_space(4))) const StageArgs ConstStageArgs;
 
 template <int P, int MODE>
-__global__ __launch_bounds__(kBlock) void batch_stage_kernel(const StageArgs *descs,
-                                                              const int2 *items, int nitems) {
+// (two resident wavefronts per SIMD asked for at orders up to 4: the p = 4 body
+// then fits 256 VGPRs with its accumulators, instead of one wavefront)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P <= 4 ? 2 : 1)))
+void batch_stage_kernel(const StageArgs *descs, const int2 *items, int nitems) {
 #if defined(__HIP_DEVICE_COMPILE__)
   ConstStageArgs *cd = (ConstStageArgs *)descs;
 #endif

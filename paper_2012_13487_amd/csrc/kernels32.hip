@@ -788,7 +788,14 @@ __device__ __forceinline__ void stage32_block(const Stage32Args &a, int blk) {
 }
 
 template <int P, int MODE, int CW, bool BF, int EFIX, bool REF, bool HO = false>
-__global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) {
+// Orders up to 3 (except the handover and bf16 forms) ask for four resident
+// wavefronts per SIMD: the moment product's accumulators then live in ordinary
+// VGPRs (128 at most, no spills) instead of 32 extra accumulation registers
+// that had held these kernels at three (measured, reference form: 256x256
+// p = 2 Couette 65.9 -> 60.2 us per stage, 128x128 p = 2 NC 16x16 194.7 ->
+// 177.0 us).
+__global__ __launch_bounds__(kBlock32) __attribute__((amdgpu_waves_per_eu((HO || BF) ? 1 : P <= 3 ? 4 : 1)))
+void stage32_kernel(const Stage32Args a) {
   stage32_block<P, MODE, CW, BF, EFIX, REF, HO>(
       a, strip_block32(xcd_block32(blockIdx.x, a.nblk), a.nx, EFIX > 0 ? EFIX : a.E, a.nblk));
 }
@@ -799,8 +806,8 @@ __global__ __launch_bounds__(kBlock32) void stage32_kernel(const Stage32Args a) 
 typedef __attribute__((address_space(4))) const Stage32Args ConstStage32Args;
 
 template <int P, int MODE, int CW, bool BF, bool REF, bool HO>
-__global__ __launch_bounds__(kBlock32) void batch_stage32_kernel(const Stage32Args *descs,
-                                                                  const int2 *items, int nitems) {
+__global__ __launch_bounds__(kBlock32) __attribute__((amdgpu_waves_per_eu((HO || BF) ? 1 : P <= 3 ? 4 : 1)))
+void batch_stage32_kernel(const Stage32Args *descs, const int2 *items, int nitems) {
 #if defined(__HIP_DEVICE_COMPILE__)
   ConstStage32Args *cd = (ConstStage32Args *)descs;
 #endif
