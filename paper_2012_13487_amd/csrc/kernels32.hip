@@ -807,7 +807,8 @@ typedef __attribute__((address_space(4))) const Stage32Args ConstStage32Args;
 
 template <int P, int MODE, int CW, bool BF, bool REF, bool HO>
 __global__ __launch_bounds__(kBlock32) __attribute__((amdgpu_waves_per_eu((HO || BF) ? 1 : P <= 3 ? 4 : 1)))
-void batch_stage32_kernel(const Stage32Args *descs, const int2 *items, int nitems) {
+void batch_stage32_kernel(const Stage32Args *descs,
+                                                                  const int2 *items, int nitems) {
 #if defined(__HIP_DEVICE_COMPILE__)
   ConstStage32Args *cd = (ConstStage32Args *)descs;
 #endif
