@@ -1064,13 +1064,15 @@ __device__ __forceinline__ void stage_block(const StageArgs &a, int blk, int til
 // One work-group per (element block, velocity tile); the general kernel.
 // FK: 0 velocity-tiled blocks, 1 fused blocks, 2 fused blocks of one element.
 template <int P, int MODE, int FK>
-// Fused blocks of orders 1-3 ask for three resident wavefronts per SIMD: the
-// compiler then keeps the moment product's accumulators in ordinary VGPRs
-// (168 at most, no spills) instead of 32 extra accumulation registers, which
-// had capped these kernels at two (measured: 256x256 p = 2 Couette, 16
-// elements per block, 199 -> 157 us per stage; 128x128 p = 2 NC 16x16, one
-// element, 448 -> 380 us).
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((FK >= 1 && P <= 3) ? 3 : 1)))
+// Fused blocks of orders 1-3 with the moment product ask for three resident
+// wavefronts per SIMD: the compiler then keeps the product's accumulators in
+// ordinary VGPRs (168 at most, no spills) instead of 32 extra accumulation
+// registers, which had capped these kernels at two (measured: 256x256 p = 2
+// Couette, 16 elements per block, 199 -> 157 us per stage; 128x128 p = 2
+// NC 16x16, one element, 448 -> 380 us).  The handover kernel (FK = 3) has no
+// product and measured slower with the request (91 -> 102 us per stage on
+// the 64x64 p = 3 cavity).
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((FK == 1 || FK == 2) && P <= 3 ? 3 : 1)))
 void stage_kernel(const StageArgs a) {
   const int blk = strip_block(xcd_block(blockIdx.x, a.nblk), a.nx, a.log2E, a.nblk);
   // Code layouts chosen by measurement: the fused block with the run-time
