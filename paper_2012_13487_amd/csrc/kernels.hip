@@ -1097,9 +1097,10 @@ void stage_kernel(const StageArgs a) {
 typedef __attribute__((address_space(4))) const StageArgs ConstStageArgs;
 
 template <int P, int MODE>
-// (two resident wavefronts per SIMD asked for at orders up to 4: the p = 4 body
-// then fits 256 VGPRs with its accumulators, instead of one wavefront)
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P <= 4 ? 2 : 1)))
+// (two resident wavefronts per SIMD asked for at order 4: its body then fits
+// 256 VGPRs with the accumulators, instead of one wavefront; lower orders run
+// two either way)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(P == 4 ? 2 : 1)))
 void batch_stage_kernel(const StageArgs *descs, const int2 *items, int nitems) {
 #if defined(__HIP_DEVICE_COMPILE__)
   ConstStageArgs *cd = (ConstStageArgs *)descs;
