@@ -1069,10 +1069,12 @@ template <int P, int MODE, int FK>
 // ordinary VGPRs (168 at most, no spills) instead of 32 extra accumulation
 // registers, which had capped these kernels at two (measured: 256x256 p = 2
 // Couette, 16 elements per block, 199 -> 157 us per stage; 128x128 p = 2
-// NC 16x16, one element, 448 -> 380 us).  The handover kernel (FK = 3) has no
-// product and measured slower with the request (91 -> 102 us per stage on
-// the 64x64 p = 3 cavity).
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((FK == 1 || FK == 2) && P <= 3 ? 3 : 1)))
+// NC 16x16, one element, 448 -> 380 us); so do velocity tiles of order 3
+// (64x64 p = 3 NC 24x24, tiles of 320 + 256: 318 -> 285 us; order 1 measured
+// slower, 805 -> 874 us).  The handover kernel (FK = 3) has no product and
+// measured slower with the request (91 -> 102 us per stage on the 64x64 p = 3
+// cavity).
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(((FK == 1 || FK == 2) && P <= 3) || (FK == 0 && P == 3) ? 3 : 1)))
 void stage_kernel(const StageArgs a) {
   const int blk = strip_block(xcd_block(blockIdx.x, a.nblk), a.nx, a.log2E, a.nblk);
   // Code layouts chosen by measurement: the fused block with the run-time
