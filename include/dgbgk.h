@@ -59,7 +59,7 @@ typedef enum {
   DGBGK_EDEVICE = -3,    /* HIP runtime error or no usable gfx950 device     */
   DGBGK_ENONFINITE = -4, /* the state or its right-hand side is not finite   */
   DGBGK_ESTATE = -5,     /* call out of order (e.g. stepping before init)    */
-  DGBGK_ENOTSUP = -6     /* valid request this build does not implement      */
+  DGBGK_ENOTSUP = -6     /* valid request the library does not implement     */
 } dgbgk_status;
 
 typedef enum { DGBGK_BC_PERIODIC = 0, DGBGK_BC_DIFFUSE_WALL = 1 } dgbgk_bc;
@@ -74,7 +74,7 @@ typedef enum { DGBGK_BC_PERIODIC = 0, DGBGK_BC_DIFFUSE_WALL = 1 } dgbgk_bc;
  *     arrays stay FP64 f (converted on the device).
  *   DGBGK_FP32_BF16MMA: as DGBGK_FP32, with the volume term's contractions
  *     Dr g, Ds g on bf16 matrix cores with FP32 accumulation (DGBGK_ENOTSUP
- *     where this build has no such kernel).
+ *     where the library has no such kernel).
  *   DGBGK_FP32_REF: the reference form.  The state is f = f_r + g with an FP64
  *     reference f_r (not streamed by the stages) and an FP32 correction g in
  *     the RK registers.  The transport part of the right-hand side (volume

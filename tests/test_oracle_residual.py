@@ -1,7 +1,7 @@
 """Pins of the oracle's steady-state residual and total mass against what fixes
 them independently of the oracle's own code.
 
-The residual (this build's reading of the north-star's "residual 1e-6"; the
+The residual (the reading of "residual 1e-6" used here for steadiness; the
 paper judges steadiness by state differences, Sec. III.A and III.B) is the
 largest rate of change of the conserved moments rho, rho u_x, rho u_y over the
 nodes, made dimensionless by L_ref / (rho_ref U_ref) with rho_ref = 1,
